@@ -1,0 +1,244 @@
+"""Benchmark of the sparse Fourier transform hot path on one MI355X.
+
+Workload: N = 2^22 complex64, s = 64 unit-magnitude random-phase frequencies
+uniform in B, complex white Gaussian noise at 20 dB (dmsft6 plan).  A step is
+one batched call (sft_execute_many) over --batch signals, drawn from --distinct
+resident inputs (more than 512 MB, so the 256 MB Infinity Cache cannot hold
+them).  The same inputs are also run through the plain per-call path
+(sft_execute in a loop) for the batched-vs-plain comparison and its latency
+distribution.
+
+Prints one JSON line (rank 0).  `value` is batched SFTs/s with inputs resident
+in HBM.  `roofline` covers the kernel with the largest share of the timed
+region, measured live with HIP events on the launch stream.  `cpu_baseline`
+times the FP64 oracle on a bounded sample of the same inputs on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (published; packed FP32)
+
+METRIC = "SFTs/s + p50/p99 latency, batched vs plain, N=2^22 s=64, rel ℓ2 err≤1e-3"
+WORKLOAD = "plain_n2e22_s64_20db"
+
+
+def kernel_work(info: dict) -> dict:
+    """Algorithmic bytes and flops of one transform, per kernel.
+
+    k_gather : reads the 2 kappa + 1 window entries of every node (8 B each) and
+               writes Q complex64 samples per node; 8 (2 kappa + 1) flops per
+               sample (complex multiply-add of a real-weighted tap with a band
+               phasor).
+    k_dft    : reads the Q M samples and writes the Q M bins (8 B each); flops of
+               the radix-2 stages (5 P log2 s1 per DFT) and the direct p-point
+               stage (8 P p per DFT).
+    """
+    Q, M, taps, s1 = info["Q"], info["M"], 2 * info["kappa"] + 1, info["s1"]
+    gather_bytes = M * taps * 8 + Q * M * 8
+    gather_flops = Q * M * taps * 8
+    dft_bytes = 2 * Q * M * 8
+    lg = int(math.log2(s1))
+    dft_flops = Q * sum(5 * P * lg + 8 * P * p for P, p in zip(info["P"], info["primes"]))
+    return {"k_gather": (gather_bytes, gather_flops), "k_dft": (dft_bytes, dft_flops)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--distinct", type=int, default=32)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--latency-calls", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the transform would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1706_02740_amd as sft
+    import siggen
+
+    sft.require_device()
+    torch.cuda.init()
+    wl = siggen.WORKLOADS[WORKLOAD]
+    N, s = wl["N"], wl["s"]
+    plan = sft.Plan(N, s)
+    info = plan.info
+
+    t0 = time.time()
+    sigs = [siggen.workload(WORKLOAD, seed) for seed in range(args.distinct)]
+    fs = [torch.from_numpy(sg.f32).cuda() for sg in sigs]
+    torch.cuda.synchronize()
+    print(f"[bench] {args.distinct} inputs generated and resident in {time.time() - t0:.1f}s "
+          f"({args.distinct * N * 8 / 2**20:.0f} MiB)", file=sys.stderr, flush=True)
+
+    B = args.batch
+    plans = [plan] * B
+    inputs = [fs[i % args.distinct] for i in range(B)]
+    outs = [(torch.empty(s, dtype=torch.int64, device="cuda"), torch.empty(s, dtype=torch.complex64, device="cuda"))
+            for _ in range(B)]
+    counts = torch.empty(B, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    # ---- batched: warmup, then K timed steps with per-kernel HIP events
+    for _ in range(args.warmup):
+        sft.execute_many(plans, inputs, outs, counts, stream)
+    torch.cuda.synchronize()
+    sft.profile_reset()
+    sft.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sft.execute_many(plans, inputs, outs, counts, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sft.profile_enable(False)
+    kern = {}
+    for kid, name in sft.KERNEL_NAMES.items():
+        n, ms = sft.profile_read(kid)
+        kern[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n if n else 0.0}
+    batched_s = (t1 - t0)
+    batched_rate = B * args.steps / batched_s
+    ms_per_step = 1e3 * batched_s / args.steps
+    print(f"[bench] batched: {ms_per_step:.3f} ms/step, {batched_rate:.0f} SFT/s", file=sys.stderr, flush=True)
+
+    # ---- plain: back-to-back sft_execute calls, then per-call latency
+    pouts = plan.outputs()
+    for i in range(min(8, B)):
+        plan.execute(inputs[i], pouts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        for i in range(B):
+            plan.execute(inputs[i], pouts)
+    torch.cuda.synchronize()
+    plain_rate = B * args.plain_steps / (time.perf_counter() - t0)
+    lat = []
+    for i in range(args.latency_calls):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        plan.execute(fs[i % args.distinct], pouts)
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - a))
+    lat = np.array(lat)
+    # batched latency: every signal of a step completes with its step
+    blat = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sft.execute_many(plans, inputs, outs, counts, stream)
+        torch.cuda.synchronize()
+        blat.append(1e3 * (time.perf_counter() - a))
+    blat = np.array(blat)
+    print(f"[bench] plain: {plain_rate:.0f} SFT/s, p50 {np.percentile(lat, 50):.3f} ms", file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel
+    work = kernel_work(info)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    roof = None
+    if dom in work and kern[dom]["avg_ms"] > 0:
+        byts, flops = work[dom]
+        avg_s = kern[dom]["avg_ms"] * 1e-3
+        if dom == "k_gather":
+            ach = byts * B / avg_s / 1e9
+            roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "algorithmic_bytes_per_launch": byts * B, "avg_launch_ms": kern[dom]["avg_ms"]}
+        else:
+            ach = flops * B / avg_s / 1e12
+            roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                    "algorithmic_flops_per_launch": flops * B, "avg_launch_ms": kern[dom]["avg_ms"]}
+    gb = work["k_gather"][0] * B / (kern["k_gather"]["avg_ms"] * 1e-3) / 1e9 if kern["k_gather"]["avg_ms"] else 0.0
+
+    # ---- accuracy and CPU baseline (FP64 oracle, bounded sample)
+    cpu = None
+    acc = None
+    if not args.no_cpu:
+        import oracle
+        op = oracle.make_plan(N, s)
+        done = 0
+        rels = []
+        c0 = time.perf_counter()
+        while done < args.distinct and (done == 0 or time.perf_counter() - c0 < args.cpu_seconds):
+            wo, co = oracle.sft(op, sigs[done].f32)
+            done += 1
+        cpu_s = time.perf_counter() - c0
+        cpu = {"value": done / cpu_s, "unit": "SFT/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} of the {args.distinct} resident N=2^22 s=64 20 dB inputs, FP64 numpy oracle, one thread",
+               "seconds": cpu_s}
+        supports_equal = True
+        for i in range(done):
+            w, c, n = plan.execute(fs[i], pouts)
+            torch.cuda.synchronize()
+            k = int(n.item())
+            wg, cg = w.cpu().numpy()[:k], c.cpu().numpy()[:k]
+            wo, co = oracle.sft(op, sigs[i].f32)
+            if sorted(wg.tolist()) != sorted(wo.tolist()):
+                supports_equal = False
+                continue
+            ref = dict(zip(wo.tolist(), co))
+            rels.append(math.sqrt(sum(abs(x - ref[int(q)]) ** 2 for q, x in zip(wg, cg)) / sum(abs(v) ** 2 for v in co)))
+        truth = []
+        for i in range(min(done, 8)):
+            w, c, n = plan.execute(fs[i], pouts)
+            k = int(n.item())
+            ref = dict(zip(sigs[i].freqs.tolist(), sigs[i].coefs))
+            wg, cg = w.cpu().numpy()[:k], c.cpu().numpy()[:k]
+            truth.append(math.sqrt(sum(abs(x - ref.get(int(q), 0)) ** 2 for q, x in zip(wg, cg)) / s))
+        acc = {"signals": done, "supports_equal_vs_oracle": supports_equal,
+               "rel_l2_vs_oracle_max": max(rels) if rels else None,
+               "rel_l2_vs_truth_mean": float(np.mean(truth)) if truth else None}
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * 2 ** 20 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC, "value": batched_rate, "unit": "SFT/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "N": N, "s": s, "snr_db": 20, "preset": "dmsft6",
+                   "batch": B, "distinct_inputs": args.distinct, "path": "sft_execute_many"},
+        "batched": {"sft_per_s": batched_rate, "batch_latency_ms_p50": float(np.percentile(blat, 50)),
+                    "batch_latency_ms_p99": float(np.percentile(blat, 99))},
+        "plain": {"sft_per_s": plain_rate, "latency_ms_p50": float(np.percentile(lat, 50)),
+                  "latency_ms_p99": float(np.percentile(lat, 99)), "calls": int(len(lat))},
+        "filtered_samples_per_s": batched_rate * info["Q"] * info["M"],
+        "gather_algorithmic_GBps": gb,
+        "kernels": kern,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy": acc,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

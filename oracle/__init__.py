@@ -22,12 +22,13 @@ from .plan import (Params, Plan, make_plan, PRESET_DMSFT6, PRESET_DMSFT4,
                    PRESET_THEORY)
 from .transform import (node_geometry, window_weight, ghat, filtered_samples,
                   short_dft, heavy_bins, crt, representative_in_band,
-                  class_depth, candidates, vote_count, median_estimate, sft, sft_trace)
+                  class_depth, candidates, vote_count, accepted_by_vote, median_estimate, sft, sft_trace)
 
 __all__ = [
     "Params", "Plan", "make_plan", "PRESET_DMSFT6", "PRESET_DMSFT4",
     "PRESET_THEORY", "node_geometry", "window_weight", "ghat",
     "filtered_samples", "short_dft", "heavy_bins", "crt",
-    "representative_in_band", "class_depth", "candidates", "vote_count", "median_estimate",
+    "representative_in_band", "class_depth", "candidates", "vote_count", "accepted_by_vote",
+    "median_estimate",
     "sft", "sft_trace",
 ]

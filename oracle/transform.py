@@ -20,8 +20,10 @@ for each band b = 1..Q (Algorithm 1, lines 3-4):
      modulus of the tuple the c heaviest bins of the class (c^G <= 64), combine
      one kept bin per modulus, solve w = a (mod s1), w = h_g (mod p_g) by the
      CRT and keep the representative of w in B, if there is one.
-  5. majority vote: keep w if more than K/2 of the moduli have
-     (w mod P_j) among their heavy bins ("more than half", Appendix B).
+  5. majority vote ("more than half" of the moduli, Appendix B): the G moduli
+     of the tuple that produced w hold heavy bins at w by construction, so the
+     vote is taken over the other K - G moduli: keep w if more than half of
+     them have (w mod P_j) among their heavy bins (for some producing tuple).
   6. estimate: z_w = median_j Re E_b[j][w mod P_j] + i median_j Im(...).
   7. line 9: the s largest |z_w| (ties to the smaller w) form R_temp.
   8. lines 10-11: keep w in [q_b - L, q_b + L) and B; divide by
@@ -141,8 +143,9 @@ def class_depth(G: int) -> int:
     return c
 
 
-def candidates(plan: Plan, heavy, E) -> list:
-    """Candidate frequencies of one band from the heavy bins of its K DFTs.
+def candidates(plan: Plan, heavy, E) -> dict:
+    """Candidate frequencies of one band from the heavy bins of its K DFTs,
+    mapped to the indices of the CRT tuples that produce them.
 
     In each CRT tuple and residue class a mod s1, the heavy bins of every
     modulus of the tuple that lie in class a are ranked by |E|^2 (ties to the
@@ -151,8 +154,8 @@ def candidates(plan: Plan, heavy, E) -> list:
     """
     s1 = plan.s1
     depth = class_depth(plan.G)
-    found = set()
-    for tup in plan.tuples:
+    found = {}
+    for t, tup in enumerate(plan.tuples):
         moduli = [s1] + [plan.primes[j] for j in tup]
         M = 1
         for m in moduli:
@@ -172,12 +175,19 @@ def candidates(plan: Plan, heavy, E) -> list:
                 residues = [a] + [h % plan.primes[j] for h, j in zip(combo, tup)]
                 w = representative_in_band(crt(residues, moduli), M, plan.N)
                 if w is not None:
-                    found.add(w)
-    return sorted(found)
+                    found.setdefault(w, set()).add(t)
+    return dict(sorted(found.items()))
 
 
-def vote_count(plan: Plan, heavy_sets, w: int) -> int:
-    return sum(1 for j in range(plan.K) if (w % plan.P[j]) in heavy_sets[j])
+def vote_count(plan: Plan, heavy_sets, w: int, exclude=()) -> int:
+    """Number of moduli j (outside `exclude`) whose heavy bins contain w mod P_j."""
+    return sum(1 for j in range(plan.K) if j not in exclude and (w % plan.P[j]) in heavy_sets[j])
+
+
+def accepted_by_vote(plan: Plan, heavy_sets, w: int, tuples) -> bool:
+    """More than half of the moduli outside a producing tuple agree."""
+    outside = plan.K - plan.G
+    return any(2 * vote_count(plan, heavy_sets, w, plan.tuples[t]) > outside for t in tuples)
 
 
 def median_estimate(plan: Plan, E, w: int) -> complex:
@@ -192,8 +202,8 @@ def _band(plan: Plan, f: np.ndarray, b: int, keep: bool):
     heavy_sets = [set(int(h) for h in Hj) for Hj in heavy]
     cands = candidates(plan, heavy, E)
     accepted = []
-    for w in cands:
-        if 2 * vote_count(plan, heavy_sets, w) > plan.K:
+    for w, tuples in cands.items():
+        if accepted_by_vote(plan, heavy_sets, w, tuples):
             accepted.append((w, median_estimate(plan, E, w)))
     # Algorithm 1, line 9: the s-sparse output of the inner algorithm
     r_temp = sorted(accepted, key=lambda wz: (-abs(wz[1]), wz[0]))[: plan.s]

@@ -1,0 +1,534 @@
+// C ABI of libsft: plans, device tables, workspaces, launches, profiling.
+#include <math.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sft_internal.h"
+
+using namespace sft;
+
+// ------------------------------------------------------------- errors ----
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+    return fail(SFT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// --------------------------------------------------------------- plans ----
+struct sft_plan_s {
+    sft_plan_info info;
+    SigDesc hdesc;          // host copy (device pointers filled in)
+    SigDesc* ddesc = nullptr;
+    void* tables = nullptr; // one allocation for every table
+    void* ws = nullptr;     // workspace of sft_execute
+    WorkspaceLayout wl;
+    IoDesc ws_io;           // workspace slices (f and outputs unset)
+    size_t footprint = 0;
+    size_t lds[SFT_KERNEL_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    int blocks[SFT_KERNEL_COUNT] = {0, 0, 0, 0, 0, 0, 0};   // per transform; 0 = kernel not used
+    bool split = false;     // short DFTs too large for one workgroup's LDS
+    int device = 0;
+    hipStream_t last_stream = nullptr;
+};
+
+static IoDesc carve(void* base, const WorkspaceLayout& wl) {
+    IoDesc io;
+    memset(&io, 0, sizeof(io));
+    char* p = static_cast<char*>(base);
+    io.S = reinterpret_cast<float2*>(p); p += wl.S;
+    io.E = reinterpret_cast<float2*>(p); p += wl.E;
+    io.H = reinterpret_cast<int32_t*>(p); p += wl.H;
+    io.Hoff = reinterpret_cast<int32_t*>(p); p += wl.Hoff;
+    io.Rw = reinterpret_cast<int64_t*>(p); p += wl.Rw;
+    io.Rv = reinterpret_cast<double2*>(p); p += wl.Rv;
+    io.Rn = reinterpret_cast<int32_t*>(p); p += wl.Rn;
+    io.status = reinterpret_cast<int32_t*>(p);
+    return io;
+}
+
+static std::mutex g_cfg_mu;
+static std::map<int, int> g_max_lds;   // device -> max dynamic LDS per workgroup (configured)
+
+static int device_lds_limit(int dev, int* out) {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    auto it = g_max_lds.find(dev);
+    if (it != g_max_lds.end()) {
+        *out = it->second;
+        return SFT_OK;
+    }
+    int v = 0;
+    HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+    HIP_TRY(configure_kernels(v), "hipFuncSetAttribute");
+    g_max_lds[dev] = v;
+    *out = v;
+    return SFT_OK;
+}
+
+extern "C" {
+
+int sft_params_default(sft_params* p, int32_t preset) {
+    if (!p) return fail(SFT_EINVAL, "params pointer is NULL");
+    if (preset < 0 || preset > 2) return fail(SFT_EINVAL, "unknown preset");
+    memset(p, 0, sizeof(*p));
+    p->preset = preset;
+    return SFT_OK;
+}
+
+int sft_plan_describe(int64_t N, int32_t s, const sft_params* p, sft_plan_info* out) {
+    if (!out) return fail(SFT_EINVAL, "info pointer is NULL");
+    const char* why = "";
+    const int rc = derive_plan(N, s, p, out, &why);
+    if (rc != SFT_OK) return fail(rc, why);
+    return SFT_OK;
+}
+
+void sft_plan_destroy(sft_plan_t plan) {
+    if (!plan) return;
+    if (plan->ws) (void)hipFree(plan->ws);
+    if (plan->tables) (void)hipFree(plan->tables);
+    if (plan->ddesc) (void)hipFree(plan->ddesc);
+    delete plan;
+}
+
+int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) {
+    if (!out) return fail(SFT_EINVAL, "plan pointer is NULL");
+    *out = nullptr;
+    sft_plan_info info;
+    const char* why = "";
+    int rc = derive_plan(N, s, p, &info, &why);
+    if (rc != SFT_OK) return fail(rc, why);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    int lds_limit = 0;
+    if ((rc = device_lds_limit(dev, &lds_limit)) != SFT_OK) return rc;
+
+    sft_plan_s* pl = new sft_plan_s();
+    pl->info = info;
+    pl->device = dev;
+    fill_desc(info, &pl->hdesc);
+    SigDesc& d = pl->hdesc;
+    const size_t lds_cap = (size_t)lds_limit - 256;   // room for the kernels' static LDS
+    const int path = p ? p->dft_path : 0;
+    if (path < 0 || path > 2) {
+        delete pl;
+        return fail(SFT_EINVAL, "dft_path must be 0, 1 or 2");
+    }
+    pl->split = path == 2 || (path == 0 && dft_lds_bytes(d) > lds_cap);
+    pl->lds[SFT_KERNEL_GATHER] = 0;
+    pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d);
+    pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
+    pl->blocks[SFT_KERNEL_GATHER] = gather_blocks(d);
+    pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);
+    pl->blocks[SFT_KERNEL_MERGE] = merge_blocks(d);
+    if (!pl->split) {
+        pl->lds[SFT_KERNEL_DFT] = dft_lds_bytes(d);
+        pl->blocks[SFT_KERNEL_DFT] = dft_blocks(d);
+    } else {
+        pl->lds[SFT_KERNEL_DFT_ROWS] = rows_lds_bytes(d);
+        pl->lds[SFT_KERNEL_DFT_COLS] = cols_lds_bytes(d);
+        pl->lds[SFT_KERNEL_SELECT] = select_lds_bytes(d);
+        pl->blocks[SFT_KERNEL_DFT_ROWS] = rows_blocks(d);
+        pl->blocks[SFT_KERNEL_DFT_COLS] = cols_blocks(d);
+        pl->blocks[SFT_KERNEL_SELECT] = select_blocks(d);
+    }
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
+        if (pl->lds[k] > lds_cap) {
+            delete pl;
+            return fail(SFT_EUNSUPPORTED, "plan needs more LDS per workgroup than the device holds");
+        }
+    }
+
+    // ---- tables (FP64 on the host, rounded once to FP32)
+    const int taps = d.taps;
+    const size_t n_band = (size_t)d.Q * taps;
+    const size_t n_tws1 = d.s1 >= 2 ? (size_t)d.s1 / 2 : 1;
+    size_t n_twp = 0;
+    for (int j = 0; j < d.K; ++j) n_twp += d.p[j];
+    std::vector<float2> band(n_band), tws1(n_tws1), twp(n_twp);
+    std::vector<float> rate(d.Q);
+    for (int b = 0; b < d.Q; ++b) {
+        const int64_t q = info.q_first + 2 * (int64_t)b * info.L;
+        rate[b] = (float)((double)q / (double)N);
+        for (int i = 0; i < taps; ++i) {
+            const int64_t o = i - d.kappa;
+            int64_t m = (q % N) * o % N;
+            if (m < 0) m += N;
+            const double ang = -2.0 * M_PI * ((double)m / (double)N);
+            band[(size_t)b * taps + i] = make_float2((float)cos(ang), (float)sin(ang));
+        }
+    }
+    for (size_t k = 0; k < n_tws1; ++k) {
+        const double ang = -2.0 * M_PI * (double)k / (double)d.s1;
+        tws1[k] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+    size_t o = 0;
+    for (int j = 0; j < d.K; ++j)
+        for (int m = 0; m < d.p[j]; ++m, ++o) {
+            const double ang = -2.0 * M_PI * (double)m / (double)d.p[j];
+            twp[o] = make_float2((float)cos(ang), (float)sin(ang));
+        }
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al(d.Q * 4);
+    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate;
+    hipError_t e = hipMalloc(&pl->tables, tbytes);
+    if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(tables) failed"); }
+    char* tb = static_cast<char*>(pl->tables);
+    d.bandtab = reinterpret_cast<const float2*>(tb);
+    d.tw_s1 = reinterpret_cast<const float2*>(tb + b_band);
+    d.tw_p = reinterpret_cast<const float2*>(tb + b_band + b_tws1);
+    d.rate = reinterpret_cast<const float*>(tb + b_band + b_tws1 + b_twp);
+    e = hipMemcpy(tb, band.data(), n_band * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tb + b_band, tws1.data(), n_tws1 * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1, twp.data(), n_twp * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1 + b_twp, rate.data(), d.Q * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(tables)"); }
+    e = hipMalloc(&pl->ddesc, sizeof(SigDesc));
+    if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(descriptor) failed"); }
+    e = hipMemcpy(pl->ddesc, &d, sizeof(SigDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(descriptor)"); }
+
+    // ---- workspace of sft_execute
+    pl->wl = workspace_layout(info);
+    e = hipMalloc(&pl->ws, pl->wl.total);
+    if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(workspace) failed"); }
+    pl->ws_io = carve(pl->ws, pl->wl);
+    pl->footprint = tbytes + sizeof(SigDesc) + pl->wl.total;
+    *out = pl;
+    return SFT_OK;
+}
+
+int sft_plan_get_info(const sft_plan_t plan, sft_plan_info* out) {
+    if (!plan || !out) return fail(SFT_EINVAL, "NULL argument");
+    *out = plan->info;
+    return SFT_OK;
+}
+
+int sft_plan_footprint(const sft_plan_t plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(SFT_EINVAL, "NULL argument");
+    *bytes = plan->footprint;
+    return SFT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ profiling ----
+namespace {
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    struct Pending { int kernel; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t launches[SFT_KERNEL_COUNT] = {};
+    double total_ms[SFT_KERNEL_COUNT] = {};
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    void drain() {
+        for (auto& p : pending) {
+            (void)hipEventSynchronize(p.b);
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                launches[p.kernel] += 1;
+                total_ms[p.kernel] += ms;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+};
+Profiler g_prof;
+
+template <class F>
+hipError_t timed(int kernel, hipStream_t st, F&& launch) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        on = g_prof.on;
+    }
+    if (!on) return launch();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        a = g_prof.get();
+        b = g_prof.get();
+    }
+    (void)hipEventRecord(a, st);
+    hipError_t e = launch();
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.push_back({kernel, a, b});
+    if (g_prof.pending.size() > 4096) g_prof.drain();
+    return e;
+}
+
+using LaunchFn = hipError_t (*)(const BatchArgs&, int, size_t, hipStream_t);
+
+hipError_t launch_gather_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_gather(a, b, st); }
+hipError_t launch_merge_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_merge(a, b, st); }
+
+// Launch order of the pipeline and the launcher of each kernel id.
+const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER, SFT_KERNEL_DFT, SFT_KERNEL_DFT_ROWS, SFT_KERNEL_DFT_COLS,
+                                      SFT_KERNEL_SELECT, SFT_KERNEL_IDENTIFY, SFT_KERNEL_MERGE};
+const char* kNames[SFT_KERNEL_COUNT] = {"launch(gather)", "launch(dft)", "launch(identify)", "launch(merge)",
+                                        "launch(dft_rows)", "launch(dft_cols)", "launch(select)"};
+
+LaunchFn launcher(int k) {
+    switch (k) {
+        case SFT_KERNEL_GATHER: return launch_gather_l;
+        case SFT_KERNEL_DFT: return launch_dft;
+        case SFT_KERNEL_IDENTIFY: return launch_identify;
+        case SFT_KERNEL_MERGE: return launch_merge_l;
+        case SFT_KERNEL_DFT_ROWS: return launch_dft_rows;
+        case SFT_KERNEL_DFT_COLS: return launch_dft_cols;
+        default: return launch_select;
+    }
+}
+
+// Enqueue the pipeline.  prefix[k] is the device prefix table of kernel k
+// (batched) or unused (single transform).
+int enqueue(BatchArgs a, const int blocks[SFT_KERNEL_COUNT], const size_t lds[SFT_KERNEL_COUNT],
+            const int32_t* const prefix[SFT_KERNEL_COUNT], hipStream_t st) {
+    for (int o = 0; o < SFT_KERNEL_COUNT; ++o) {
+        const int k = kOrder[o];
+        if (blocks[k] <= 0) continue;
+        a.prefix = prefix ? prefix[k] : nullptr;
+        LaunchFn fn = launcher(k);
+        const hipError_t e = timed(k, st, [&] { return fn(a, blocks[k], lds[k], st); });
+        if (e != hipSuccess) return hip_fail(e, kNames[k]);
+    }
+    return SFT_OK;
+}
+
+// ----------------------------------------------------- batch arenas ----
+// One per (device, stream): the workspace of every transform of an
+// sft_execute_many call plus its descriptor tables.  Calls on one stream are
+// ordered, so the arena is reused; it grows (after a stream synchronisation)
+// when a larger batch arrives.
+struct Arena {
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* meta = nullptr;
+    size_t meta_bytes = 0;
+    void* staging = nullptr;     // pinned host copy of meta
+    hipEvent_t staged = nullptr; // the last upload from staging has been consumed
+};
+std::mutex g_arena_mu;
+std::map<std::pair<int, void*>, Arena*> g_arenas;
+
+Arena* arena_for(int dev, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    auto key = std::make_pair(dev, (void*)st);
+    auto it = g_arenas.find(key);
+    if (it != g_arenas.end()) return it->second;
+    Arena* a = new Arena();
+    g_arenas[key] = a;
+    return a;
+}
+}  // namespace
+
+extern "C" {
+
+int sft_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return SFT_OK;
+}
+
+int sft_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.drain();
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
+        g_prof.launches[k] = 0;
+        g_prof.total_ms[k] = 0.0;
+    }
+    return SFT_OK;
+}
+
+int sft_profile_read(int32_t kernel, int64_t* launches, double* total_ms) {
+    if (kernel < 0 || kernel >= SFT_KERNEL_COUNT) return fail(SFT_EINVAL, "unknown kernel id");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.drain();
+    if (launches) *launches = g_prof.launches[kernel];
+    if (total_ms) *total_ms = g_prof.total_ms[kernel];
+    return SFT_OK;
+}
+
+int sft_execute(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_dev, void* out_coeffs_dev,
+                int32_t* out_count_dev, void* stream) {
+    if (!plan || !f_dev || !out_freqs_dev || !out_coeffs_dev) return fail(SFT_EINVAL, "NULL argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.desc_one = plan->ddesc;
+    a.io_one = plan->ws_io;
+    a.io_one.f = static_cast<const float2*>(f_dev);
+    a.io_one.out_w = out_freqs_dev;
+    a.io_one.out_c = static_cast<float2*>(out_coeffs_dev);
+    a.io_one.out_n = out_count_dev;
+    a.nsig = 1;
+    plan->last_stream = st;
+    return enqueue(a, plan->blocks, plan->lds, nullptr, st);
+}
+
+int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* f_dev,
+                     int64_t* const* out_freqs_dev, void* const* out_coeffs_dev, int32_t* out_counts_dev,
+                     void* stream) {
+    if (count < 0) return fail(SFT_EINVAL, "count must be >= 0");
+    if (count == 0) return SFT_OK;
+    if (!plans || !f_dev || !out_freqs_dev || !out_coeffs_dev) return fail(SFT_EINVAL, "NULL argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    // sizes
+    std::vector<size_t> wsoff(count);
+    size_t ws_total = 0;
+    size_t lds[SFT_KERNEL_COUNT] = {};
+    for (int i = 0; i < count; ++i) {
+        const sft_plan_s* p = plans[i];
+        if (!p || !f_dev[i] || !out_freqs_dev[i] || !out_coeffs_dev[i]) return fail(SFT_EINVAL, "NULL entry");
+        if (p->device != dev) return fail(SFT_EINVAL, "plan belongs to another device");
+        wsoff[i] = ws_total;
+        ws_total += p->wl.total;
+        for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
+            if (p->lds[k] > lds[k]) lds[k] = p->lds[k];
+    }
+    // meta layout: [count] desc pointers | [count] IoDesc | SFT_KERNEL_COUNT x [count+1] prefixes
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t m_desc = al(sizeof(void*) * count);
+    const size_t m_io = al(sizeof(IoDesc) * count);
+    const size_t m_pre = al(sizeof(int32_t) * (count + 1));
+    const size_t meta_total = m_desc + m_io + SFT_KERNEL_COUNT * m_pre;
+
+    Arena* ar = arena_for(dev, st);
+    if (ar->staged) HIP_TRY(hipEventSynchronize(ar->staged), "hipEventSynchronize");
+    if (ar->ws_bytes < ws_total || ar->meta_bytes < meta_total) {
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (ar->ws_bytes < ws_total) {
+            if (ar->ws) (void)hipFree(ar->ws);
+            ar->ws = nullptr;
+            ar->ws_bytes = 0;
+            if (hipMalloc(&ar->ws, ws_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch workspace) failed");
+            ar->ws_bytes = ws_total;
+        }
+        if (ar->meta_bytes < meta_total) {
+            if (ar->meta) (void)hipFree(ar->meta);
+            if (ar->staging) (void)hipHostFree(ar->staging);
+            ar->meta = nullptr;
+            ar->staging = nullptr;
+            ar->meta_bytes = 0;
+            if (hipMalloc(&ar->meta, meta_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch meta) failed");
+            if (hipHostMalloc(&ar->staging, meta_total, hipHostMallocDefault) != hipSuccess)
+                return fail(SFT_ENOMEM, "hipHostMalloc(batch staging) failed");
+            ar->meta_bytes = meta_total;
+        }
+        if (!ar->staged) HIP_TRY(hipEventCreateWithFlags(&ar->staged, hipEventDisableTiming), "hipEventCreate");
+    }
+    char* hs = static_cast<char*>(ar->staging);
+    const SigDesc** hdesc = reinterpret_cast<const SigDesc**>(hs);
+    IoDesc* hio = reinterpret_cast<IoDesc*>(hs + m_desc);
+    int32_t* hpre[SFT_KERNEL_COUNT];
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) hpre[k] = reinterpret_cast<int32_t*>(hs + m_desc + m_io + k * m_pre);
+    int blocks[SFT_KERNEL_COUNT] = {};
+    for (int i = 0; i < count; ++i) {
+        const sft_plan_s* p = plans[i];
+        hdesc[i] = p->ddesc;
+        IoDesc io = carve(static_cast<char*>(ar->ws) + wsoff[i], p->wl);
+        io.f = static_cast<const float2*>(f_dev[i]);
+        io.out_w = out_freqs_dev[i];
+        io.out_c = static_cast<float2*>(out_coeffs_dev[i]);
+        io.out_n = out_counts_dev ? out_counts_dev + i : nullptr;
+        hio[i] = io;
+        for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
+            hpre[k][i] = blocks[k];
+            blocks[k] += p->blocks[k];
+        }
+    }
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) hpre[k][count] = blocks[k];
+    HIP_TRY(hipMemcpyAsync(ar->meta, ar->staging, meta_total, hipMemcpyHostToDevice, st), "hipMemcpyAsync(meta)");
+    HIP_TRY(hipEventRecord(ar->staged, st), "hipEventRecord");
+    char* dm = static_cast<char*>(ar->meta);
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.descs_many = reinterpret_cast<const SigDesc* const*>(dm);
+    a.io_many = reinterpret_cast<const IoDesc*>(dm + m_desc);
+    a.nsig = count;
+    const int32_t* dpre[SFT_KERNEL_COUNT];
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) dpre[k] = reinterpret_cast<const int32_t*>(dm + m_desc + m_io + k * m_pre);
+    return enqueue(a, blocks, lds, dpre, st);
+}
+
+int sft_plan_status(sft_plan_t plan, int32_t* flags) {
+    if (!plan) return fail(SFT_EINVAL, "NULL plan");
+    HIP_TRY(hipStreamSynchronize(plan->last_stream), "hipStreamSynchronize");
+    int32_t v = 0;
+    HIP_TRY(hipMemcpy(&v, plan->ws_io.status, 4, hipMemcpyDeviceToHost), "hipMemcpy(status)");
+    if (flags) *flags = v;
+    if (v != 0) return fail(SFT_EOVERFLOW, "a device-side capacity was exceeded");
+    return SFT_OK;
+}
+
+int sft_plan_fetch(const sft_plan_t plan, int32_t what, void* dst, size_t bytes, size_t* bytes_needed) {
+    if (!plan) return fail(SFT_EINVAL, "NULL plan");
+    const sft_plan_info& in = plan->info;
+    const void* src = nullptr;
+    size_t need = 0;
+    switch (what) {
+        case SFT_FETCH_SAMPLES: src = plan->ws_io.S; need = (size_t)in.Q * in.M * 8; break;
+        case SFT_FETCH_BINS: src = plan->ws_io.E; need = (size_t)in.Q * in.M * 8; break;
+        case SFT_FETCH_HEAVY: src = plan->ws_io.H; need = (size_t)in.K * in.Q * in.T * 4; break;
+        case SFT_FETCH_BANDS: need = (size_t)in.Q * 4 + (size_t)in.Q * in.s * 24; break;
+        default: return fail(SFT_EINVAL, "unknown fetch kind");
+    }
+    if (bytes_needed) *bytes_needed = need;
+    if (!dst) return SFT_OK;
+    if (bytes < need) return fail(SFT_EINVAL, "destination too small");
+    HIP_TRY(hipStreamSynchronize(plan->last_stream), "hipStreamSynchronize");
+    if (what != SFT_FETCH_BANDS) {
+        HIP_TRY(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost), "hipMemcpy(fetch)");
+        return SFT_OK;
+    }
+    // counts[Q], then Q*s records {int64 w; double re; double im}, band b's at b*s
+    char* o = static_cast<char*>(dst);
+    HIP_TRY(hipMemcpy(o, plan->ws_io.Rn, (size_t)in.Q * 4, hipMemcpyDeviceToHost), "hipMemcpy(fetch)");
+    std::vector<int64_t> w((size_t)in.Q * in.s);
+    std::vector<double2> v((size_t)in.Q * in.s);
+    HIP_TRY(hipMemcpy(w.data(), plan->ws_io.Rw, w.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy(fetch)");
+    HIP_TRY(hipMemcpy(v.data(), plan->ws_io.Rv, v.size() * 16, hipMemcpyDeviceToHost), "hipMemcpy(fetch)");
+    char* rec = o + (size_t)in.Q * 4;
+    for (size_t i = 0; i < w.size(); ++i) {
+        memcpy(rec + i * 24, &w[i], 8);
+        memcpy(rec + i * 24 + 8, &v[i].x, 8);
+        memcpy(rec + i * 24 + 16, &v[i].y, 8);
+    }
+    return SFT_OK;
+}
+
+const char* sft_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

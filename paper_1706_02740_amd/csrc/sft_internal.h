@@ -1,0 +1,117 @@
+// Internal definitions shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+#include "sft.h"
+
+namespace sft {
+
+constexpr int kMaxK = SFT_MAX_MODULI;
+constexpr int kMaxG = 7;
+constexpr int kThreads = 256;          // every kernel runs 256-thread workgroups (4 wave64)
+constexpr int kBandChunk = 16;         // bands accumulated per pass of the gather kernel
+constexpr int kAcceptCap = 4096;       // accepted candidates per band kept in LDS
+constexpr int kMergeCap = 4096;        // band results merged per signal in LDS
+constexpr int kRowElems = 4096;        // complex values per workgroup in the split path's row FFTs
+constexpr int kColChunk = 64;          // columns per workgroup in the split path's p-point DFTs
+
+// Status bits written by the device.
+constexpr int kStatusAcceptOverflow = 1;
+constexpr int kStatusMergeOverflow = 2;
+
+// Per-plan constants, uploaded once at plan creation.  Every kernel reads it
+// through a device pointer; all reads are wave-uniform.
+struct SigDesc {
+    int64_t N;
+    int64_t L;
+    int64_t q_first;        // q_b = q_first + 2 b L
+    int64_t lo, hi;         // B = [lo, hi]
+    int32_t s, kappa, taps, Q, K, G, s1, log2s1, T, depth, M, Tpow2;
+    float   inv2sig2;       // 1 / (2 sigma_t^2)
+    float   wnorm;          // 1 / (2 pi sigma_t): W(v) = wnorm exp(-v^2 inv2sig2)
+    float   a_first;        // q_first / N    (per-node band phase rate, in turns)
+    float   a_step;         // 2 L / N
+    double  c1sq_half;      // c1^2 / 2
+    double  ghat0;          // 1 / sqrt(2 pi)
+    int32_t p[kMaxK];
+    int32_t P[kMaxK];
+    int32_t Moff[kMaxK + 1];
+    int32_t pinv_s1[kMaxK];  // p_j^{-1} mod s1   (Good-Thomas output map)
+    int32_t s1inv_p[kMaxK];  // s1^{-1} mod p_j
+    int32_t tw_off[kMaxK];   // offset of modulus j's p-point twiddles in tw_p
+    // CRT tuples: component 0 is s1, components 1..G are the tuple's primes.
+    int32_t tup_j[2][kMaxG];
+    int64_t tup_M[2];
+    int64_t tup_Mi[2][kMaxG + 1];
+    int32_t tup_inv[2][kMaxG + 1];
+    int32_t tup_mod[2][kMaxG + 1];
+    // device tables owned by the plan
+    const float2* bandtab;   // [Q][taps]: exp(-2 pi i ((q_b (i - kappa)) mod N) / N)
+    const float2* tw_s1;     // [s1/2]: exp(-2 pi i k / s1)
+    const float2* tw_p;      // concatenated [p_j]: exp(-2 pi i m / p_j)
+    const float* rate;       // [Q]: q_b / N, the per-node band phase rate in turns
+};
+
+// Per-transform pointers: input, outputs and workspace slices.
+struct IoDesc {
+    const float2* f;
+    int64_t* out_w;
+    float2* out_c;
+    int32_t* out_n;
+    float2* S;        // [Q*M] filtered samples
+    float2* E;        // [Q*M] short-DFT bins
+    int32_t* H;       // [K*Q*T] heavy bins
+    int32_t* Hoff;    // [K*Q*(s1+1)] class offsets into H
+    int64_t* Rw;      // [Q*s] band results: frequencies
+    double2* Rv;      // [Q*s] band results: coefficients
+    int32_t* Rn;      // [Q] band result counts
+    int32_t* status;  // [1]
+};
+
+// Kernel launch argument: one transform (descs_many == nullptr) or a batch.
+struct BatchArgs {
+    const SigDesc* desc_one;
+    IoDesc io_one;
+    const SigDesc* const* descs_many;  // [nsig] device array of plan descriptors
+    const IoDesc* io_many;             // [nsig]
+    const int32_t* prefix;             // [nsig+1] first block of each signal for this kernel
+    int32_t nsig;
+};
+
+// Per-signal workspace sizes in bytes (each slice 256-byte aligned).
+struct WorkspaceLayout {
+    size_t S, E, H, Hoff, Rw, Rv, Rn, status, total;
+};
+
+// plan.cpp
+int derive_plan(int64_t N, int32_t s, const sft_params* p, sft_plan_info* out, const char** why);
+void fill_desc(const sft_plan_info& info, SigDesc* d);
+WorkspaceLayout workspace_layout(const sft_plan_info& info);
+size_t dft_lds_bytes(const SigDesc& d);
+
+// kernels.hip: host-side launchers (enqueue only).  Block counts per signal:
+int gather_blocks(const SigDesc& d);
+int dft_blocks(const SigDesc& d);
+int identify_blocks(const SigDesc& d);
+int merge_blocks(const SigDesc& d);
+hipError_t launch_gather(const BatchArgs& a, int blocks, hipStream_t st);
+hipError_t launch_dft(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+// split short-DFT path for blocks larger than one workgroup's LDS
+int rows_blocks(const SigDesc& d);
+int cols_blocks(const SigDesc& d);
+int select_blocks(const SigDesc& d);
+size_t rows_lds_bytes(const SigDesc& d);
+size_t cols_lds_bytes(const SigDesc& d);
+size_t select_lds_bytes(const SigDesc& d);
+hipError_t launch_dft_rows(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_dft_cols(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_merge(const BatchArgs& a, int blocks, hipStream_t st);
+hipError_t configure_kernels(int max_lds);
+size_t identify_lds_bytes(const SigDesc& d);
+size_t merge_lds_bytes();
+
+}  // namespace sft

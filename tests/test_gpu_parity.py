@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded complex64 inputs.
+
+Tolerances (derived in the design doc from the FP32 arithmetic of each step).
+FP32 rounding errors scale with the magnitudes summed, not with a result that
+cancels, so each block's scale is  A = max(max|S_oracle|, max|f| * sum_i W_i)
+(sum_i W_i ~ 1/sqrt(2 pi) is the window's total weight):
+  filtered samples   |S_gpu - S_oracle| <= 2e-5 * A per (band, modulus) block
+  short-DFT bins     |E_gpu - E_oracle| <= 2e-5 * max(max|E_oracle|, A)
+  heavy bins         equal sets, except bins whose oracle |E| lies within
+                     3e-5 * max(max|E|, A) of the T-th largest (a rounding-order swap)
+  end to end         supports bit-equal; coefficients rel-l2 <= 1e-3
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import siggen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SAMPLE_TOL = 2e-5
+BIN_TOL = 2e-5
+COEF_TOL = 1e-3
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(f):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(f, dtype=np.complex64))).cuda()
+
+
+def gpu_run(plan, f32):
+    w, c, n = plan.execute(dev(f32))
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    k = int(n.item())
+    return w.cpu().numpy()[:k], c.cpu().numpy()[:k]
+
+
+def assert_same_result(wg, cg, wo, co, tol=COEF_TOL):
+    assert sorted(wg.tolist()) == sorted(wo.tolist())
+    ref = dict(zip(wo.tolist(), co))
+    num = sum(abs(c - ref[int(w)]) ** 2 for w, c in zip(wg, cg))
+    den = sum(abs(v) ** 2 for v in co)
+    rel = float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
+    assert rel <= tol, rel
+    # order: (|c| desc, w asc) on the GPU side
+    mags = np.abs(cg)
+    assert np.all(mags[:-1] >= mags[1:] * (1 - 1e-6))
+    return rel
+
+
+def _oplan(N, s, kw):
+    return oracle.make_plan(N, s, oracle.Params(**{k: v for k, v in kw.items() if k != "dft_path"}))
+
+
+INTERMEDIATE_CASES = [
+    ("plain_n2e14_s8_seed0", 2 ** 14, 8, None, {}, 0),
+    ("prime_n100003_s20_30db", 100_003, 20, 30.0, {}, 1),
+    ("n98304_s12_dmsft4", 3 * 2 ** 15, 12, 40.0, {"preset": 1}, 2),
+    ("n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2}, 3),
+    ("n31_s1", 31, 1, None, {}, 4),
+    ("n64_s64", 64, 64, None, {}, 5),
+    ("split_prime_n100003_s20_30db", 100_003, 20, 30.0, {"dft_path": 2}, 1),
+    ("split_n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2, "dft_path": 2}, 3),
+]
+
+
+def _okw(kw):
+    return {k: v for k, v in kw.items() if k != "dft_path"}
+
+
+@pytest.mark.parametrize("name,N,s,snr,kw,seed", INTERMEDIATE_CASES, ids=[c[0] for c in INTERMEDIATE_CASES])
+def test_intermediates_match_oracle(gpu, name, N, s, snr, kw, seed):
+    say("case", name)
+    sig = siggen.sparse_signal(N, s, seed=seed, snr_db=snr)
+    f32 = sig.f32
+    plan = gpu.Plan(N, s, **kw)
+    op = _oplan(N, s, kw)
+    wg, cg = gpu_run(plan, f32)
+    S_all = plan.fetch(gpu.FETCH_SAMPLES)
+    E_all = plan.fetch(gpu.FETCH_BINS)
+    H_all = plan.fetch(gpu.FETCH_HEAVY)
+    in_scale = float(np.max(np.abs(f32))) / np.sqrt(2 * np.pi)
+    for b in range(op.Q):
+        for j in range(op.K):
+            So = oracle.filtered_samples(op, f32, b, j)
+            Sg = gpu.samples_natural(plan, S_all, b, j)
+            scale = max(np.max(np.abs(So)), in_scale, 1e-30)
+            assert np.max(np.abs(Sg - So)) <= SAMPLE_TOL * scale, (b, j)
+            Eo = oracle.short_dft(So)
+            Eg = gpu.bins_natural(plan, E_all, b, j)
+            escale = max(np.max(np.abs(Eo)), scale)
+            assert np.max(np.abs(Eg - Eo)) <= BIN_TOL * escale, (b, j)
+            Ho = set(oracle.heavy_bins(Eo, op.T).tolist())
+            Hg = set(gpu.heavy_block(plan, H_all, b, j).tolist())
+            assert len(Hg) == op.T
+            diff = Ho ^ Hg
+            if diff:
+                mag = np.abs(Eo)
+                thr = np.sort(mag)[::-1][op.T - 1]
+                for h in diff:
+                    assert abs(mag[h] - thr) <= 3e-5 * escale, (b, j, h)
+    wo, co = oracle.sft(op, f32)
+    assert_same_result(wg, cg, wo, co)
+
+
+END_TO_END = [
+    ("plain_n2e14_s8", 2 ** 14, 8, None, "unit", {}, range(0, 6)),
+    ("ragged_n2621441_s200_30db", 5 * 2 ** 19 + 1, 200, 30.0, "unit", {}, range(0, 1)),
+    ("n3x2e20_s16_30db", 3 * 2 ** 20, 16, 30.0, "unit", {}, range(0, 1)),
+    ("n2e18_s256_30db", 2 ** 18, 256, 30.0, "unit", {}, range(0, 1)),
+    ("loguniform_n1000003_s64_40db", 1_000_003, 64, 40.0, "loguniform", {}, range(0, 1)),
+]
+
+
+@pytest.mark.parametrize("name,N,s,snr,mag,kw,seeds", END_TO_END, ids=[c[0] for c in END_TO_END])
+def test_end_to_end_matches_oracle(gpu, name, N, s, snr, mag, kw, seeds):
+    plan = gpu.Plan(N, s, **kw)
+    op = _oplan(N, s, kw)
+    for seed in seeds:
+        say("case", name, "seed", seed)
+        sig = siggen.sparse_signal(N, s, seed=seed, snr_db=snr, magnitude=mag)
+        wg, cg = gpu_run(plan, sig.f32)
+        wo, co = oracle.sft(op, sig.f32)
+        assert_same_result(wg, cg, wo, co)
+        # every true frequency is found (these inputs are exactly s-sparse plus noise)
+        assert set(wg.tolist()) == set(sig.freqs.tolist())
+
+
+def test_headline_n2e22_s64_20db(gpu):
+    """The headline shape, plain path and batched path, against the oracle."""
+    N, s = 2 ** 22, 64
+    plan = gpu.Plan(N, s)
+    op = _oplan(N, s, {})
+    sigs = [siggen.workload("plain_n2e22_s64_20db", seed) for seed in (0, 1)]
+    fs = [dev(sg.f32) for sg in sigs]
+    outs, counts = gpu.execute_many([plan] * 8, [fs[i % 2] for i in range(8)])
+    torch.cuda.synchronize()
+    for seed, sg in enumerate(sigs):
+        say("headline seed", seed)
+        wg, cg = gpu_run(plan, sg.f32)
+        wo, co = oracle.sft(op, sg.f32)
+        assert_same_result(wg, cg, wo, co)
+        assert set(wo.tolist()) == set(sg.freqs.tolist())
+        for i in range(seed, 8, 2):
+            k = int(counts[i].item())
+            assert np.array_equal(outs[i][0].cpu().numpy()[:k], wg)
+            assert np.array_equal(outs[i][1].cpu().numpy()[:k], cg)
+
+
+def test_prime_n10000019_s128_40db(gpu):
+    N, s = 10_000_019, 128
+    say("prime length")
+    plan = gpu.Plan(N, s)
+    op = _oplan(N, s, {})
+    sg = siggen.workload("prime_n10000019_s128_40db", 0)
+    wg, cg = gpu_run(plan, sg.f32)
+    wo, co = oracle.sft(op, sg.f32)
+    assert_same_result(wg, cg, wo, co)
+    assert set(wo.tolist()) == set(sg.freqs.tolist())
+
+
+def test_batched_equals_plain_mixed_plans(gpu):
+    shapes = [(2 ** 14, 8), (100_003, 20), (2 ** 16, 40), (2 ** 14, 8), (31, 1), (3 * 2 ** 15, 12)]
+    plans = {}
+    for N, s in shapes:
+        if (N, s) not in plans:
+            plans[(N, s)] = gpu.Plan(N, s)
+    sigs = [siggen.sparse_signal(N, s, seed=50 + i, snr_db=30.0) for i, (N, s) in enumerate(shapes)]
+    fs = [dev(sg.f32) for sg in sigs]
+    pl = [plans[sh] for sh in shapes]
+    say("batched mixed", len(shapes))
+    outs, counts = gpu.execute_many(pl, fs)
+    torch.cuda.synchronize()
+    for i, (p, f) in enumerate(zip(pl, fs)):
+        w, c, n = p.execute(f)
+        torch.cuda.synchronize()
+        k = int(n.item())
+        assert int(counts[i].item()) == k
+        assert np.array_equal(outs[i][0].cpu().numpy(), w.cpu().numpy())
+        assert np.array_equal(outs[i][1].cpu().numpy(), c.cpu().numpy())
+    # an empty batch is a no-op
+    gpu.execute_many([], [])
+
+
+@pytest.mark.parametrize("N,s,snr,kw", [(2 ** 14, 8, 30.0, {}), (100_003, 20, 20.0, {}),
+                                        (2 ** 16, 100, 10.0, {"preset": 1}), (2 ** 14, 8, None, {"preset": 2})])
+def test_split_dft_path_equals_in_lds_path(gpu, N, s, snr, kw):
+    """The split short-DFT kernels perform the same arithmetic in the same order
+    as the in-LDS kernel: bins, heavy sets and outputs are bitwise equal."""
+    say("split vs lds", N, s, kw)
+    sg = siggen.sparse_signal(N, s, seed=13, snr_db=snr)
+    f = dev(sg.f32)
+    res = []
+    for path in (1, 2):
+        plan = gpu.Plan(N, s, dft_path=path, **kw)
+        w, c, n = plan.execute(f)
+        torch.cuda.synchronize()
+        res.append((w.cpu().numpy(), c.cpu().numpy(), plan.fetch(gpu.FETCH_BINS), plan.fetch(gpu.FETCH_HEAVY)))
+    for x, y in zip(res[0], res[1]):
+        assert np.array_equal(x, y)
+
+
+def test_repeat_runs_are_bitwise_identical(gpu):
+    sg = siggen.sparse_signal(2 ** 16, 30, seed=77, snr_db=10.0)
+    plan = gpu.Plan(sg.N, sg.s)
+    f = dev(sg.f32)
+    a = [t.cpu().numpy().copy() for t in plan.execute(f)]
+    b = [t.cpu().numpy().copy() for t in plan.execute(f)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_unfilled_slots_are_zero(gpu):
+    """Pure noise with a large s: fewer than s frequencies pass the vote; the
+    remaining output slots hold w = 0, c = 0 and the count says how many are set."""
+    N, s = 4096, 40
+    rng = np.random.default_rng(3)
+    f = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64) * 1e-3
+    sg = siggen.sparse_signal(N, 2, seed=9)
+    f = f + sg.f32
+    plan = gpu.Plan(N, s)
+    w, c, n = plan.execute(dev(f))
+    torch.cuda.synchronize()
+    k = int(n.item())
+    wn, cn = w.cpu().numpy(), c.cpu().numpy()
+    assert np.all(wn[k:] == 0) and np.all(cn[k:] == 0)
+    assert 2 <= k <= s
+    assert set(wn[:k].tolist()) >= set(sg.freqs.tolist())
+    assert len(set(wn[:k].tolist())) == k

@@ -143,7 +143,8 @@ def test_band_edge_frequencies():
 def test_candidates_equal_bruteforce_definition():
     """A candidate is exactly a w in B whose residue bin, in every modulus of some
     CRT tuple, is heavy and among the class_depth(G) heaviest of its residue
-    class mod s1 (brute force over all of B)."""
+    class mod s1 (brute force over all of B); the vote, R_temp and band test
+    follow their definitions."""
     sig = siggen.sparse_signal(2 ** 14, 8, seed=41, snr_db=10)
     plan = make_plan(sig.N, sig.s)
     lo, hi = plan.band_lo, plan.band_hi
@@ -161,23 +162,40 @@ def test_candidates_equal_bruteforce_definition():
                 cls.sort(key=lambda h: (-m2[h], h))
                 top |= set(cls[:depth])
             kept.append(np.array(sorted(top)))
-        brute = set()
-        for tup in plan.tuples:
+        brute = {}
+        for t, tup in enumerate(plan.tuples):
             ok = np.ones(w_all.shape, bool)
             for j in tup:
                 ok &= np.isin(np.mod(w_all, plan.P[j]), kept[j])
-            brute |= set(w_all[ok].tolist())
-        assert brute == set(info["candidates"])
-        # vote: accepted iff more than half of the K moduli have a heavy bin at w
+            for w in w_all[ok].tolist():
+                brute.setdefault(w, set()).add(t)
+        assert brute == info["candidates"]
+        # vote: accepted iff, for a producing tuple, more than half of the K - G
+        # other moduli have a heavy bin at w
         acc = {w for w, _ in info["accepted"]}
-        for w in info["candidates"]:
-            votes = sum((w % plan.P[j]) in heavy_sets[j] for j in range(plan.K))
-            assert (w in acc) == (votes > plan.K / 2)
+        for w, tups in info["candidates"].items():
+            ok = False
+            for t in tups:
+                others = [j for j in range(plan.K) if j not in plan.tuples[t]]
+                votes = sum((w % plan.P[j]) in heavy_sets[j] for j in others)
+                ok |= votes > len(others) / 2
+            assert (w in acc) == ok
         # R_temp is the s largest |z| (ties to the smaller w); kept = R_temp inside the band
         ranked = sorted(info["accepted"], key=lambda wz: (-abs(wz[1]), wz[0]))[: plan.s]
         assert ranked == info["r_temp"]
         q = plan.q[b]
         assert [w for w, _ in info["kept"]] == [w for w, _ in ranked if q - plan.L <= w < q + plan.L and lo <= w <= hi]
+
+
+def test_ghost_combinations_are_rejected():
+    """Two strong frequencies in one residue class mod s1 give CRT combinations
+    that mix their bins across a tuple's moduli.  Such a ghost has heavy bins in
+    its own tuple by construction; the vote over the other moduli rejects it,
+    so weak true frequencies are not displaced (log-uniform magnitudes, 40 dB)."""
+    plan = make_plan(1_000_003, 64)
+    sig = siggen.sparse_signal(1_000_003, 64, seed=0, snr_db=40.0, magnitude="loguniform")
+    fr, co = oracle.sft(plan, sig.f32)
+    assert set(fr.tolist()) == set(sig.freqs.tolist())
 
 
 def test_class_depth():

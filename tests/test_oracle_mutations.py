@@ -78,6 +78,10 @@ def _bad_window(plan, v):
     return np.exp(-(x ** 2) / (2.0 * plan.c1 * plan.c1)) / (plan.c1 * plan.N * math.sqrt(2 * math.pi))
 
 
+def _bad_vote_all_moduli(plan, heavy_sets, w, tuples):
+    return 2 * sum((w % plan.P[j]) in heavy_sets[j] for j in range(plan.K)) > plan.K
+
+
 MUTATIONS = [
     ("filtered_samples", _bad_samples_sign, lambda: pins.test_filtered_samples_closed_form(0)),
     ("filtered_samples", _bad_samples_short_window, pins.test_window_extent_with_a_unit_impulse),
@@ -89,6 +93,8 @@ MUTATIONS = [
     ("ghat", _bad_ghat, lambda: pins.test_ghat_matches_numerical_fourier_coefficients(64)),
     ("window_weight", _bad_window, lambda: pins.test_window_weight_is_g_over_N(64, 3.3)),
     ("ghat", _bad_ghat, e2e.test_band_edge_frequencies),
+    ("accepted_by_vote", _bad_vote_all_moduli, e2e.test_candidates_equal_bruteforce_definition),
+    ("accepted_by_vote", _bad_vote_all_moduli, e2e.test_ghost_combinations_are_rejected),
 ]
 
 
