@@ -183,8 +183,8 @@ SFT_API int sft_plan_status(sft_plan_t plan, int32_t* flags);
  *                      entry n1 + s1*n2 is the node k = (n1 p_j + n2 s1) mod P_j.
  *   SFT_FETCH_BINS     complex64[Q * M]: short-DFT bins, same blocks; entry
  *                      k1 + s1*k2 is the bin h with h = k1 (mod s1), h = k2 (mod p_j).
- *   SFT_FETCH_HEAVY    int32[K * Q * T]: heavy bins of block (j, b) at
- *                      (j*Q + b)*T, ordered by (h mod s1, |E|^2 desc, h asc).
+ *   SFT_FETCH_HEAVY    int32[K * Q * T]: heavy bins h of block (j, b) at
+ *                      (j*Q + b)*T, in ascending Good-Thomas position.
  *   SFT_FETCH_BANDS    per band b: int32 count at [b], then (int64 w, double re,
  *                      double im) records; see the library documentation.
  * bytes_needed (may be NULL) receives the size; dst may be NULL to query.

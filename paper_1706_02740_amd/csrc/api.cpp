@@ -54,7 +54,8 @@ static IoDesc carve(void* base, const WorkspaceLayout& wl) {
     io.S = reinterpret_cast<float2*>(p); p += wl.S;
     io.E = reinterpret_cast<float2*>(p); p += wl.E;
     io.H = reinterpret_cast<int32_t*>(p); p += wl.H;
-    io.Hoff = reinterpret_cast<int32_t*>(p); p += wl.Hoff;
+    io.thr = reinterpret_cast<uint64_t*>(p); p += wl.thr;
+    io.CL = reinterpret_cast<int32_t*>(p); p += wl.CL;
     io.Rw = reinterpret_cast<int64_t*>(p); p += wl.Rw;
     io.Rv = reinterpret_cast<double2*>(p); p += wl.Rv;
     io.Rn = reinterpret_cast<int32_t*>(p); p += wl.Rn;
@@ -130,7 +131,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         return fail(SFT_EINVAL, "dft_path must be 0, 1 or 2");
     }
     pl->split = path == 2 || (path == 0 && dft_lds_bytes(d) > lds_cap);
-    pl->lds[SFT_KERNEL_GATHER] = 0;
+    pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
     pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d);
     pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
     pl->blocks[SFT_KERNEL_GATHER] = gather_blocks(d);
@@ -148,7 +149,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         pl->blocks[SFT_KERNEL_SELECT] = select_blocks(d);
     }
     for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
-        if (pl->lds[k] > lds_cap) {
+        if (k != SFT_KERNEL_GATHER && pl->lds[k] > lds_cap) {
             delete pl;
             return fail(SFT_EUNSUPPORTED, "plan needs more LDS per workgroup than the device holds");
         }
@@ -289,7 +290,10 @@ hipError_t timed(int kernel, hipStream_t st, F&& launch) {
 
 using LaunchFn = hipError_t (*)(const BatchArgs&, int, size_t, hipStream_t);
 
-hipError_t launch_gather_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_gather(a, b, st); }
+// For the gather kernel the lds argument carries the common tap count (0 = mixed).
+hipError_t launch_gather_l(const BatchArgs& a, int b, size_t taps, hipStream_t st) {
+    return launch_gather(a, b, (int)taps, st);
+}
 hipError_t launch_merge_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_merge(a, b, st); }
 
 // Launch order of the pipeline and the launcher of each kernel id.
@@ -416,7 +420,10 @@ int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* 
         wsoff[i] = ws_total;
         ws_total += p->wl.total;
         for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
-            if (p->lds[k] > lds[k]) lds[k] = p->lds[k];
+            if (k != SFT_KERNEL_GATHER && p->lds[k] > lds[k]) lds[k] = p->lds[k];
+        // one compile-time tap count when every transform shares it, else the generic kernel
+        if (i == 0) lds[SFT_KERNEL_GATHER] = p->lds[SFT_KERNEL_GATHER];
+        else if (lds[SFT_KERNEL_GATHER] != p->lds[SFT_KERNEL_GATHER]) lds[SFT_KERNEL_GATHER] = 0;
     }
     // meta layout: [count] desc pointers | [count] IoDesc | SFT_KERNEL_COUNT x [count+1] prefixes
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };

@@ -92,8 +92,41 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
 //   S_b = exp(2 pi i q_b u / N) * sum_i f[(j' + i) mod N] W(u - i) exp(-2 pi i q_b i / N)
 // with W(v) = exp(-v^2 / (2 sigma_t^2)) / (2 pi sigma_t) (the periodized Gaussian
 // divided by N, eq. Def_Periodic_Gaussian) and the second phasor from the plan's
-// exact table.
+// exact table.  The node phasors exp(2 pi i q_b u / N) follow q_{b+1} - q_b = 2L:
+// evaluated directly every kPhaseAnchor bands and by one complex product per
+// band in between.  TAPS > 0 fixes 2 kappa + 1 at compile time (the window is
+// loaded before any arithmetic); TAPS == 0 reads it from the plan.  Both forms
+// perform the same operations in the same order, so their results are equal.
 
+constexpr int kPhaseAnchor = 8;
+
+__device__ __forceinline__ float tap_weight(int32_t delta, int o, int P, float Pf, float wnorm, float inv2sig2) {
+    const float v = (float)(delta - o * P) / Pf;
+    return wnorm * expf(-v * v * inv2sig2);
+}
+
+__device__ __forceinline__ void store_bands(float2* __restrict__ S, int P, int b0, int nb, const float2* acc,
+                                            float u, const float* __restrict__ rate, float step_rate) {
+    float sn, cs;
+    sincospif(2.0f * u * step_rate, &sn, &cs);
+    const float2 step = make_float2(cs, sn);
+    float2 ph = make_float2(1.f, 0.f);
+#pragma unroll
+    for (int bb = 0; bb < kBandChunk; ++bb) {
+        if (bb < nb) {
+            if (((b0 + bb) % kPhaseAnchor) == 0) {
+                sincospif(2.0f * u * rate[b0 + bb], &sn, &cs);
+                ph = make_float2(cs, sn);
+            } else {
+                ph = make_float2(ph.x * step.x - ph.y * step.y, ph.x * step.y + ph.y * step.x);
+            }
+            S[(size_t)(b0 + bb) * P] = make_float2(acc[bb].x * ph.x - acc[bb].y * ph.y,
+                                                   acc[bb].x * ph.y + acc[bb].y * ph.x);
+        }
+    }
+}
+
+template <int TAPS>
 __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
     const Where at = locate(a);
     const SigDesc* __restrict__ d = desc_of(a, at.sig);
@@ -118,51 +151,78 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
     const int32_t delta = (int32_t)(nN - jp * P);
     const float Pf = (float)P;
     const float u = (float)delta / Pf;
-    const int kappa = d->kappa;
-    const int taps = d->taps;
+    const int kappa = TAPS > 0 ? (TAPS - 1) / 2 : d->kappa;
+    const int taps = TAPS > 0 ? TAPS : d->taps;
     const int Q = d->Q;
     const float inv2sig2 = d->inv2sig2;
     const float wnorm = d->wnorm;
     const float2* __restrict__ f = io.f;
     float2* __restrict__ S = io.S + (size_t)Q * d->Moff[j] + l;
     const float* __restrict__ rate = d->rate;
+    const float step_rate = d->a_step;
     const bool interior = (jp - kappa >= 0) && (jp + kappa < N);
 
-    for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
-        const int nb = min(kBandChunk, Q - b0);
-        float2 acc[kBandChunk];
+    if constexpr (TAPS > 0) {
+        float2 x[TAPS];
 #pragma unroll
-        for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = make_float2(0.f, 0.f);
-        const float2* __restrict__ tab = d->bandtab + (size_t)b0 * taps;
-        for (int i = 0; i < taps; ++i) {
+        for (int i = 0; i < TAPS; ++i) {
             int64_t idx = jp - kappa + i;
             if (!interior) {
                 if (idx < 0) idx += N;
                 else if (idx >= N) idx -= N;
             }
-            const float v = (float)(delta - (i - kappa) * P) / Pf;
-            const float w = wnorm * expf(-v * v * inv2sig2);
-            const float2 fv = f[idx];
-            const float xr = fv.x * w;
-            const float xi = fv.y * w;
-#pragma unroll
-            for (int bb = 0; bb < kBandChunk; ++bb) {
-                if (bb < nb) {
-                    const float2 t = tab[bb * taps + i];
-                    acc[bb].x = fmaf(xr, t.x, fmaf(-xi, t.y, acc[bb].x));
-                    acc[bb].y = fmaf(xr, t.y, fmaf(xi, t.x, acc[bb].y));
-                }
-            }
+            x[i] = f[idx];
         }
 #pragma unroll
-        for (int bb = 0; bb < kBandChunk; ++bb) {
-            if (bb < nb) {
-                float sn, cs;
-                sincospif(2.0f * u * rate[b0 + bb], &sn, &cs);
-                const float2 r = make_float2(acc[bb].x * cs - acc[bb].y * sn,
-                                             acc[bb].x * sn + acc[bb].y * cs);
-                S[(size_t)(b0 + bb) * P] = r;
+        for (int i = 0; i < TAPS; ++i) {
+            const float w = tap_weight(delta, i - kappa, P, Pf, wnorm, inv2sig2);
+            x[i] = make_float2(x[i].x * w, x[i].y * w);
+        }
+        for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
+            const int nb = min(kBandChunk, Q - b0);
+            float2 acc[kBandChunk];
+            const float2* __restrict__ tab = d->bandtab + (size_t)b0 * TAPS;
+#pragma unroll
+            for (int bb = 0; bb < kBandChunk; ++bb) {
+                acc[bb] = make_float2(0.f, 0.f);
+                if (bb < nb) {
+#pragma unroll
+                    for (int i = 0; i < TAPS; ++i) {
+                        const float2 t = tab[bb * TAPS + i];
+                        acc[bb].x = fmaf(x[i].x, t.x, fmaf(-x[i].y, t.y, acc[bb].x));
+                        acc[bb].y = fmaf(x[i].x, t.y, fmaf(x[i].y, t.x, acc[bb].y));
+                    }
+                }
             }
+            store_bands(S, P, b0, nb, acc, u, rate, step_rate);
+        }
+    } else {
+        for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
+            const int nb = min(kBandChunk, Q - b0);
+            float2 acc[kBandChunk];
+#pragma unroll
+            for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = make_float2(0.f, 0.f);
+            const float2* __restrict__ tab = d->bandtab + (size_t)b0 * taps;
+            for (int i = 0; i < taps; ++i) {
+                int64_t idx = jp - kappa + i;
+                if (!interior) {
+                    if (idx < 0) idx += N;
+                    else if (idx >= N) idx -= N;
+                }
+                const float w = tap_weight(delta, i - kappa, P, Pf, wnorm, inv2sig2);
+                const float2 fv = f[idx];
+                const float xr = fv.x * w;
+                const float xi = fv.y * w;
+#pragma unroll
+                for (int bb = 0; bb < kBandChunk; ++bb) {
+                    if (bb < nb) {
+                        const float2 t = tab[bb * taps + i];
+                        acc[bb].x = fmaf(xr, t.x, fmaf(-xi, t.y, acc[bb].x));
+                        acc[bb].y = fmaf(xr, t.y, fmaf(xi, t.x, acc[bb].y));
+                    }
+                }
+            }
+            store_bands(S, P, b0, nb, acc, u, rate, step_rate);
         }
     }
 }
@@ -182,12 +242,16 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
 // path: k_dft_rows (step A on a few rows), k_dft_cols (step B on 64 columns),
 // k_select (the selection, reading E from global memory).
 
-// Bit reversal and butterflies over `rows` rows of s1 complex values in LDS.
-__device__ void fft_rows_lds(float2* buf, int rows, int s1, int lg, const float2* __restrict__ tw) {
+// Bit reversal, then the radix-2 DIT stages of length-s1 FFTs over `rows`
+// rows in LDS.  Stages are fused in pairs: each thread loads four values,
+// applies two radix-2 stages in registers and stores them back (a leading
+// single stage when log2 s1 is odd).  tw: LDS copy of exp(-2 pi i k / s1).
+template <int NT>
+__device__ void fft_rows_lds(float2* buf, int rows, int s1, int lg, const float2* tw) {
     const int tid = (int)threadIdx.x;
     const int n = rows << lg;
     if (lg == 0) return;
-    for (int i = tid; i < n; i += kThreads) {
+    for (int i = tid; i < n; i += NT) {
         const int n1 = i & (s1 - 1);
         const int r = (int)(__brev((unsigned)n1) >> (32 - lg));
         if (n1 < r) {
@@ -198,42 +262,117 @@ __device__ void fft_rows_lds(float2* buf, int rows, int s1, int lg, const float2
         }
     }
     __syncthreads();
-    const int half_n = n >> 1;
-    for (int len = 2, ls = 1; len <= s1; len <<= 1, ++ls) {
-        const int half = len >> 1;
-        const int twstride = s1 >> ls;
-        for (int i = tid; i < half_n; i += kThreads) {
-            const int row = i >> (lg - 1);
-            const int rr = i & ((s1 >> 1) - 1);
-            const int grp = rr >> (ls - 1);
-            const int pos = rr & (half - 1);
-            const int i0 = (row << lg) + grp * len + pos;
-            const int i1 = i0 + half;
-            const float2 w = tw[pos * twstride];
-            const float2 x0 = buf[i0];
-            const float2 x1 = buf[i1];
-            const float2 y = make_float2(x1.x * w.x - x1.y * w.y, x1.x * w.y + x1.y * w.x);
-            buf[i0] = make_float2(x0.x + y.x, x0.y + y.y);
-            buf[i1] = make_float2(x0.x - y.x, x0.y - y.y);
+    int ls = 1;
+    if (lg & 1) {   // stage of length 2: twiddle 1
+        for (int i = tid; i < (n >> 1); i += NT) {
+            const float2 x0 = buf[2 * i];
+            const float2 x1 = buf[2 * i + 1];
+            buf[2 * i] = make_float2(x0.x + x1.x, x0.y + x1.y);
+            buf[2 * i + 1] = make_float2(x0.x - x1.x, x0.y - x1.y);
+        }
+        __syncthreads();
+        ls = 2;
+    }
+    for (; ls + 1 <= lg; ls += 2) {
+        const int h = 1 << (ls - 1);   // half length of stage ls
+        const int quarter = n >> 2;
+        for (int i = tid; i < quarter; i += NT) {
+            const int row = i >> (lg - 2);
+            const int rr = i & ((s1 >> 2) - 1);
+            const int blk = rr >> (ls - 1);
+            const int pos = rr & (h - 1);
+            const int b0 = (row << lg) + blk * (4 * h) + pos;
+            float2 x0 = buf[b0], x1 = buf[b0 + h], x2 = buf[b0 + 2 * h], x3 = buf[b0 + 3 * h];
+            const float2 w1 = tw[pos << (lg - ls)];
+            float2 y = make_float2(x1.x * w1.x - x1.y * w1.y, x1.x * w1.y + x1.y * w1.x);
+            x1 = make_float2(x0.x - y.x, x0.y - y.y);
+            x0 = make_float2(x0.x + y.x, x0.y + y.y);
+            y = make_float2(x3.x * w1.x - x3.y * w1.y, x3.x * w1.y + x3.y * w1.x);
+            x3 = make_float2(x2.x - y.x, x2.y - y.y);
+            x2 = make_float2(x2.x + y.x, x2.y + y.y);
+            const float2 w2 = tw[pos << (lg - ls - 1)];
+            const float2 w3 = tw[(pos + h) << (lg - ls - 1)];
+            y = make_float2(x2.x * w2.x - x2.y * w2.y, x2.x * w2.y + x2.y * w2.x);
+            buf[b0 + 2 * h] = make_float2(x0.x - y.x, x0.y - y.y);
+            buf[b0] = make_float2(x0.x + y.x, x0.y + y.y);
+            y = make_float2(x3.x * w3.x - x3.y * w3.y, x3.x * w3.y + x3.y * w3.x);
+            buf[b0 + 3 * h] = make_float2(x1.x - y.x, x1.y - y.y);
+            buf[b0 + h] = make_float2(x1.x + y.x, x1.y + y.y);
         }
         __syncthreads();
     }
 }
 
-// p-point DFT of column k1 at output row k2: sum_n2 col[n2 * stride] W_p^(n2 k2).
-__device__ __forceinline__ float2 dft_p_point(const float2* col, int stride, int p, int k2,
-                                              const float2* __restrict__ twp) {
-    float ar = 0.f, ai = 0.f;
-    int m = 0;
-    for (int n2 = 0; n2 < p; ++n2) {
-        const float2 x = col[n2 * stride];
-        const float2 w = twp[m];
-        ar = fmaf(x.x, w.x, fmaf(-x.y, w.y, ar));
-        ai = fmaf(x.x, w.y, fmaf(x.y, w.x, ai));
-        m += k2;
-        if (m >= p) m -= p;
+// Cosine/sine table of the p-point step: trig[(n - 1) h + (k - 1)] =
+// (cos, sin)(2 pi (n k mod p) / p) for n, k in [1, h], h = (p - 1) / 2, built in
+// LDS from the plan's exp(-2 pi i m / p) table.
+template <int NT>
+__device__ void build_trig(float2* trig, int p, const float2* __restrict__ twp) {
+    const int h = (p - 1) >> 1;
+    for (int i = (int)threadIdx.x; i < h * h; i += NT) {
+        const int n = i / h + 1;
+        const int k = i - (n - 1) * h + 1;
+        const float2 w = twp[(n * k) % p];
+        trig[i] = make_float2(w.x, -w.y);
     }
-    return make_float2(ar, ai);
+}
+
+constexpr int kDftKB = 8;   // output pairs (k, p - k) per work item of the p-point step
+
+// p-point DFTs of the columns of a [p][stride] block (LDS), one work item per
+// (column, group of kDftKB output pairs); results scaled by `scale` and written
+// to out[k * out_stride + column].  With h = (p - 1) / 2, a_n = x_n + x_{p-n},
+// b_n = x_n - x_{p-n}, C_k = sum_n a_n cos(2 pi n k / p), D_k = sum_n b_n sin(...):
+//   X_k = x_0 + C_k - i D_k,  X_{p-k} = x_0 + C_k + i D_k,  X_0 = x_0 + sum_n a_n.
+template <int NT>
+__device__ void dft_cols_lds(const float2* blk, int stride, int ncols, int p, const float2* trig,
+                             float2* __restrict__ out, int out_stride, float scale) {
+    const int h = (p - 1) >> 1;
+    const int ng = (h + kDftKB - 1) / kDftKB;
+    const int groups = ng > 0 ? ng : 1;
+    for (int item = (int)threadIdx.x; item < ncols * groups; item += NT) {
+        const int g = item / ncols;
+        const int c = item - g * ncols;
+        const int k0 = 1 + g * kDftKB;
+        const float2 x0 = blk[c];
+        float2 C[kDftKB], D[kDftKB];
+#pragma unroll
+        for (int kk = 0; kk < kDftKB; ++kk) {
+            C[kk] = make_float2(0.f, 0.f);
+            D[kk] = make_float2(0.f, 0.f);
+        }
+        float2 sa = make_float2(0.f, 0.f);
+        for (int n = 1; n <= h; ++n) {
+            const float2 xa = blk[n * stride + c];
+            const float2 xb = blk[(p - n) * stride + c];
+            const float2 av = make_float2(xa.x + xb.x, xa.y + xb.y);
+            const float2 bv = make_float2(xa.x - xb.x, xa.y - xb.y);
+            sa.x += av.x;
+            sa.y += av.y;
+            const float2* tr = trig + (n - 1) * h + (k0 - 1);
+#pragma unroll
+            for (int kk = 0; kk < kDftKB; ++kk) {
+                if (k0 + kk <= h) {
+                    const float2 t = tr[kk];
+                    C[kk].x = fmaf(av.x, t.x, C[kk].x);
+                    C[kk].y = fmaf(av.y, t.x, C[kk].y);
+                    D[kk].x = fmaf(bv.x, t.y, D[kk].x);
+                    D[kk].y = fmaf(bv.y, t.y, D[kk].y);
+                }
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < kDftKB; ++kk) {
+            const int k = k0 + kk;
+            if (k <= h) {
+                out[(size_t)k * out_stride + c] =
+                    make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale);
+                out[(size_t)(p - k) * out_stride + c] =
+                    make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale);
+            }
+        }
+        if (g == 0) out[c] = make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale);
+    }
 }
 
 __device__ __forceinline__ uint64_t bin_key(float2 e, int i, int lg, int s1, int P, int64_t cA, int64_t cB) {
@@ -244,108 +383,123 @@ __device__ __forceinline__ uint64_t bin_key(float2 e, int i, int lg, int s1, int
     return ((uint64_t)__float_as_uint(m2) << 32) | (uint64_t)(0xffffffffu - h);
 }
 
-__device__ __forceinline__ bool cls_key_less(int32_t ca, uint64_t ka, int32_t cb, uint64_t kb) {
-    return ca < cb || (ca == cb && ka > kb);
-}
-
-// Top-T of the P distinct keys key(i), written to H[T] sorted by (class, key
-// desc) and Hoff[s1 + 1].  skey/scls: LDS [Tp]; hist: LDS [256].
-template <class KeyF>
-__device__ void select_heavy(KeyF key, int P, int T, int Tp, int s1, uint64_t* skey, int32_t* scls,
-                             int32_t* hist, int32_t* __restrict__ H, int32_t* __restrict__ Hoff) {
-    __shared__ int32_t sh_digit, sh_need, sh_count, sh_done;
+// The T-th largest of the P distinct keys key(i), 1 <= T: a radix select over
+// 8-bit digits from the most significant one, which stops as soon as the
+// chosen digit's bucket holds exactly the keys still needed.  The keys >= the
+// returned value are exactly the T largest.  hist: LDS int32[256]; part: LDS
+// int32[4].  The digit search is a wave-shuffle scan of the 256 buckets.
+template <int NT, class KeyF>
+__device__ uint64_t kth_largest(KeyF key, int P, int T, int32_t* hist, int32_t* part) {
+    __shared__ int32_t sh_digit, sh_need, sh_done;
     const int tid = (int)threadIdx.x;
-    if (tid == 0) {
-        sh_need = T;
-        sh_done = 0;
-        sh_count = 0;
-    }
-    __syncthreads();
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    if (T >= P) return 0;
     uint64_t prefix = 0, pmask = 0;
-    for (int shift = 56; shift >= 0 && T > 0 && T < P; shift -= 8) {
-        for (int i = tid; i < 256; i += kThreads) hist[i] = 0;
+    int need = T;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += NT) hist[i] = 0;
         __syncthreads();
-        for (int i = tid; i < P; i += kThreads) {
+        for (int i = tid; i < P; i += NT) {
             const uint64_t k = key(i);
             if ((k & pmask) == prefix) atomicAdd(&hist[(int)((k >> shift) & 255u)], 1);
         }
         __syncthreads();
-        if (tid == 0) {
-            int need = sh_need, cum = 0, dsel = 0;
-            for (int dg = 255; dg >= 0; --dg) {
-                if (cum + hist[dg] >= need) {
-                    dsel = dg;
-                    break;
-                }
-                cum += hist[dg];
+        int c = 0, x = 0;
+        if (tid < 256) {   // bucket 255 - tid: a descending suffix count
+            c = hist[255 - tid];
+            x = c;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(x, off);
+                if (lane >= off) x += y;
             }
-            sh_digit = dsel;
-            sh_need = need - cum;
-            sh_done = (hist[dsel] == need - cum) ? 1 : 0;
+            if (lane == 63) part[wid] = x;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            int base = 0;
+            for (int w = 0; w < wid; ++w) base += part[w];
+            const int incl = base + x;
+            const int excl = incl - c;
+            if (excl < need && incl >= need) {
+                sh_digit = 255 - tid;
+                sh_need = need - excl;
+                sh_done = (c == need - excl) ? 1 : 0;
+            }
         }
         __syncthreads();
         prefix |= (uint64_t)sh_digit << shift;
         pmask |= (uint64_t)255u << shift;
-        const int done = sh_done;
-        __syncthreads();
-        if (done) break;
+        need = sh_need;
+        if (sh_done) break;   // sh_* change again only after the next pass's second barrier
     }
-    const uint64_t thr = (T >= P) ? 0ull : prefix;   // the selected keys are those >= thr
-    if (T > 0) {
-        for (int i = tid; i < P; i += kThreads) {
-            const uint64_t k = key(i);
+    return prefix;
+}
+
+// Exclusive block-wide prefix sum of one value per thread.  part: LDS int32[NT/64].
+template <int NT>
+__device__ int block_exclusive_sum(int v, int32_t* part) {
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) part[wid] = x;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wid; ++w) base += part[w];
+    __syncthreads();
+    return base + x - v;
+}
+
+// Heavy bins of one block (keys >= thr).  Writes the threshold, the heavy bins
+// in ascending Good-Thomas position (H[T]), and for every residue class c mod
+// s1, which is column c of the [p][s1] layout, the `depth` heaviest heavy bins
+// of the class in descending key order (CL[c * depth + e], -1 where fewer).
+template <int NT, class KeyF>
+__device__ void emit_heavy(KeyF key, int P, int s1, int p, int depth, uint64_t thr, int32_t* part,
+                           int32_t* __restrict__ H, uint64_t* __restrict__ thr_out, int32_t* __restrict__ CL) {
+    const int tid = (int)threadIdx.x;
+    if (tid == 0) *thr_out = thr;
+    for (int c = tid; c < s1; c += NT) {
+        uint64_t top[kMaxDepth];
+#pragma unroll
+        for (int e = 0; e < kMaxDepth; ++e) top[e] = 0;   // every real key is > 0
+        for (int k2 = 0; k2 < p; ++k2) {
+            uint64_t k = key(k2 * s1 + c);
             if (k >= thr) {
-                const int pos = atomicAdd(&sh_count, 1);
-                if (pos < Tp) {
-                    const uint32_t h = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
-                    skey[pos] = k;
-                    scls[pos] = (int32_t)(h & (uint32_t)(s1 - 1));
-                }
-            }
-        }
-    }
-    __syncthreads();
-    for (int i = tid; i < Tp; i += kThreads) {
-        if (i >= T) {
-            skey[i] = 0;
-            scls[i] = 0x7fffffff;
-        }
-    }
-    __syncthreads();
-    for (int kk = 2; kk <= Tp; kk <<= 1) {
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < Tp; i += kThreads) {
-                const int ixj = i ^ jj;
-                if (ixj > i) {
-                    const bool up = (i & kk) == 0;
-                    const int32_t ci = scls[i], cx = scls[ixj];
-                    const uint64_t ki = skey[i], kx = skey[ixj];
-                    const bool sw = up ? cls_key_less(cx, kx, ci, ki) : cls_key_less(ci, ki, cx, kx);
-                    if (sw) {
-                        scls[i] = cx;
-                        scls[ixj] = ci;
-                        skey[i] = kx;
-                        skey[ixj] = ki;
+#pragma unroll
+                for (int e = 0; e < kMaxDepth; ++e) {
+                    if (e < depth && k > top[e]) {
+                        const uint64_t t = top[e];
+                        top[e] = k;
+                        k = t;
                     }
                 }
             }
-            __syncthreads();
         }
+        for (int e = 0; e < depth; ++e)
+            CL[c * depth + e] = top[e] ? (int32_t)(0xffffffffu - (uint32_t)(top[e] & 0xffffffffu)) : -1;
     }
-    for (int i = tid; i < T; i += kThreads) H[i] = (int32_t)(0xffffffffu - (uint32_t)(skey[i] & 0xffffffffu));
-    for (int c = tid; c <= s1; c += kThreads) {
-        int lo = 0, hi = T;   // first index with class >= c
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (scls[mid] < c) lo = mid + 1; else hi = mid;
-        }
-        Hoff[c] = lo;
+    const int chunk = (P + NT - 1) / NT;
+    const int beg = min(P, tid * chunk);
+    const int end = min(P, beg + chunk);
+    int mine = 0;
+    for (int i = beg; i < end; ++i) mine += key(i) >= thr ? 1 : 0;
+    int o = block_exclusive_sum<NT>(mine, part);
+    for (int i = beg; i < end; ++i) {
+        const uint64_t k = key(i);
+        if (k >= thr) H[o++] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
     }
 }
 
 // One workgroup per (modulus j, band b); the whole block in LDS.
-__global__ void __launch_bounds__(kThreads) k_dft(BatchArgs a) {
+__global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NT = kDftThreads;
     const Where at = locate(a);
     const SigDesc* __restrict__ d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
@@ -358,38 +512,37 @@ __global__ void __launch_bounds__(kThreads) k_dft(BatchArgs a) {
     const int P = d->P[j];
     const int s1 = d->s1;
     const int lg = d->log2s1;
-    const int Tp = d->Tpow2;
     const int Pmax = d->P[K - 1];
+    const int hmax = (d->p[K - 1] - 1) >> 1;
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
 
     float2* buf = reinterpret_cast<float2*>(smem);
     uint64_t* keys = reinterpret_cast<uint64_t*>(smem);
-    uint64_t* skey = reinterpret_cast<uint64_t*>(smem + (size_t)Pmax * 8);
-    int32_t* scls = reinterpret_cast<int32_t*>(smem + (size_t)Pmax * 8 + (size_t)Tp * 8);
-    int32_t* hist = reinterpret_cast<int32_t*>(smem + (size_t)Pmax * 8 + (size_t)Tp * 12);
+    float2* tw = reinterpret_cast<float2*>(smem + (size_t)Pmax * 8);
+    float2* trig = tw + (s1 >> 1);
+    int32_t* hist = reinterpret_cast<int32_t*>(trig + hmax * hmax);
+    int32_t* part = hist + 256;
 
     const float2* __restrict__ S = io.S + base;
-    for (int i = tid; i < P; i += kThreads) buf[i] = S[i];
+    for (int i = tid; i < P; i += NT) buf[i] = S[i];
+    for (int i = tid; i < (s1 >> 1); i += NT) tw[i] = d->tw_s1[i];
+    build_trig<NT>(trig, p, d->tw_p + d->tw_off[j]);
     __syncthreads();
-    fft_rows_lds(buf, p, s1, lg, d->tw_s1);
+    fft_rows_lds<NT>(buf, p, s1, lg, tw);
 
     // step B; the keys below re-read E: same workgroup, ordered by the barrier
     float2* __restrict__ E = io.E + base;
-    const float2* __restrict__ twp = d->tw_p + d->tw_off[j];
-    const float invP = 1.0f / (float)P;
-    for (int i = tid; i < P; i += kThreads) {
-        const int k2 = i >> lg;
-        const int k1 = i & (s1 - 1);
-        const float2 e = dft_p_point(buf + k1, s1, p, k2, twp);
-        E[i] = make_float2(e.x * invP, e.y * invP);
-    }
+    dft_cols_lds<NT>(buf, s1, s1, p, trig, E, s1, 1.0f / (float)P);
     __syncthreads();
     const int64_t cA = (int64_t)p * d->pinv_s1[j];
     const int64_t cB = (int64_t)s1 * d->s1inv_p[j];
-    for (int i = tid; i < P; i += kThreads) keys[i] = bin_key(E[i], i, lg, s1, P, cA, cB);
+    for (int i = tid; i < P; i += NT) keys[i] = bin_key(E[i], i, lg, s1, P, cA, cB);
     __syncthreads();
-    select_heavy([&](int i) { return keys[i]; }, P, d->T, Tp, s1, skey, scls, hist,
-                 io.H + (size_t)(j * Q + b) * d->T, io.Hoff + (size_t)(j * Q + b) * (s1 + 1));
+    auto kf = [&](int i) { return keys[i]; };
+    const uint64_t thr = kth_largest<NT>(kf, P, d->T, hist, part);
+    const size_t blk = (size_t)(j * Q + b);
+    emit_heavy<NT>(kf, P, s1, p, d->depth, thr, part, io.H + blk * d->T, io.thr + blk,
+                   io.CL + blk * (size_t)s1 * d->depth);
 }
 
 // Split path, step A: block -> (modulus j, band b, chunk of rows_per rows).
@@ -424,11 +577,13 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     const int rows = min(rows_per, p - r0);
     const size_t base = (size_t)d->Q * d->Moff[j] + (size_t)b * d->P[j] + ((size_t)r0 << lg);
     float2* buf = reinterpret_cast<float2*>(smem);
+    float2* tw = buf + ((size_t)rows_per << lg);
     const int n = rows << lg;
     const float2* __restrict__ S = io.S + base;
     for (int i = tid; i < n; i += kThreads) buf[i] = S[i];
+    for (int i = tid; i < (s1 >> 1); i += kThreads) tw[i] = d->tw_s1[i];
     __syncthreads();
-    fft_rows_lds(buf, rows, s1, lg, d->tw_s1);
+    fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
     float2* __restrict__ X = io.E + base;   // the bins' buffer holds the step-A result
     for (int i = tid; i < n; i += kThreads) X[i] = buf[i];
 }
@@ -452,23 +607,20 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     const int c0 = (blk - b * nc) * C;
     const int p = d->p[j];
     const int P = d->P[j];
+    int pmax = 0;
+    for (int jj = 0; jj < d->K; ++jj) pmax = max(pmax, d->p[jj]);
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
     float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]
+    float2* trig = tile + (size_t)pmax * C;
     float2* __restrict__ E = io.E + base;
     for (int i = tid; i < p * C; i += kThreads) {
         const int n2 = i / C;
         const int k1 = c0 + (i - n2 * C);
         tile[i] = E[((size_t)n2 << lg) + k1];
     }
+    build_trig<kThreads>(trig, p, d->tw_p + d->tw_off[j]);
     __syncthreads();
-    const float2* __restrict__ twp = d->tw_p + d->tw_off[j];
-    const float invP = 1.0f / (float)P;
-    for (int i = tid; i < p * C; i += kThreads) {
-        const int k2 = i / C;
-        const int kc = i - k2 * C;
-        const float2 e = dft_p_point(tile + kc, C, p, k2, twp);
-        E[((size_t)k2 << lg) + c0 + kc] = make_float2(e.x * invP, e.y * invP);
-    }
+    dft_cols_lds<kThreads>(tile, C, C, p, trig, E + c0, s1, 1.0f / (float)P);
 }
 
 // Split path, selection: one workgroup per (modulus j, band b), E in global memory.
@@ -484,24 +636,27 @@ __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
     const int P = d->P[j];
     const int s1 = d->s1;
     const int lg = d->log2s1;
-    const int Tp = d->Tpow2;
-    uint64_t* skey = reinterpret_cast<uint64_t*>(smem);
-    int32_t* scls = reinterpret_cast<int32_t*>(smem + (size_t)Tp * 8);
-    int32_t* hist = reinterpret_cast<int32_t*>(smem + (size_t)Tp * 12);
+    int32_t* hist = reinterpret_cast<int32_t*>(smem);
+    int32_t* part = hist + 256;
     const float2* __restrict__ E = io.E + (size_t)Q * d->Moff[j] + (size_t)b * P;
     const int64_t cA = (int64_t)p * d->pinv_s1[j];
     const int64_t cB = (int64_t)s1 * d->s1inv_p[j];
-    select_heavy([&](int i) { return bin_key(E[i], i, lg, s1, P, cA, cB); }, P, d->T, Tp, s1, skey, scls, hist,
-                 io.H + (size_t)(j * Q + b) * d->T, io.Hoff + (size_t)(j * Q + b) * (s1 + 1));
+    auto kf = [&](int i) { return bin_key(E[i], i, lg, s1, P, cA, cB); };
+    const uint64_t thr = kth_largest<kThreads>(kf, P, d->T, hist, part);
+    const size_t blk = (size_t)(j * Q + b);
+    emit_heavy<kThreads>(kf, P, s1, p, d->depth, thr, part, io.H + blk * d->T, io.thr + blk,
+                         io.CL + blk * (size_t)s1 * d->depth);
 }
 
 // ---------------------------------------------------------- k_identify ----
 // One workgroup per band b.  Candidates: in CRT tuple t and residue class a,
-// one of the `depth` heaviest class-a bins of every modulus of the tuple;
+// one of the `depth` heaviest heavy class-a bins of every modulus of the tuple
+// (the class lists written with the heavy bins);
 // w = a (mod s1), w = h_g (mod p_g) by the CRT in int64, mapped into B.
 // Vote ("more than half", Appendix B): the tuple's own G moduli hold heavy bins
 // at w by construction, so (w mod P_j) must be a heavy bin for more than half of
-// the other K - G moduli.  A w produced by both tuples is accepted if either
+// the other K - G moduli; a bin is heavy when its key is at least the block's
+// threshold, the key computed from the same E value as in the selection.  A w produced by both tuples is accepted if either
 // tuple's vote passes (the two entries are equal and merged later).  Estimate:
 // componentwise median of E_b[j][w mod P_j] over all K moduli.  Then the s
 // largest |z| (ties to the smaller w), the band test w in [q_b - L, q_b + L),
@@ -535,7 +690,6 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     const int G = d->G;
     const int s1 = d->s1;
     const int lg = d->log2s1;
-    const int T = d->T;
     const int depth = d->depth;
     const int64_t lo = d->lo, hi = d->hi;
     const int nslots = 2 * s1;
@@ -547,19 +701,22 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     int32_t* pre = scratch + kThreads;
     __shared__ int32_t sh_cnt;
 
-    const int32_t* __restrict__ Hall = io.H;
-    const int32_t* __restrict__ Hoffall = io.Hoff;
+    const int32_t* __restrict__ CLall = io.CL;
+    const uint64_t* __restrict__ thr = io.thr;
     const float2* __restrict__ Eall = io.E;
+    const size_t cl_stride = (size_t)s1 * depth;   // one (modulus, band) block of class lists
 
-    // 1. combinations per (tuple, class) slot
+    // 1. combinations per (tuple, class) slot: product of the class-list lengths
     for (int slot = tid; slot < nslots; slot += kThreads) {
         const int t = slot >> lg;
         const int ac = slot & (s1 - 1);
         int cnt = 1;
         for (int g = 0; g < G; ++g) {
             const int jj = d->tup_j[t][g];
-            const int32_t* hb = Hoffall + (size_t)(jj * Q + b) * (s1 + 1);
-            cnt *= min(depth, hb[ac + 1] - hb[ac]);
+            const int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
+            int n = 0;
+            while (n < depth && cl[n] >= 0) ++n;
+            cnt *= n;
         }
         pre[slot] = cnt;
     }
@@ -583,11 +740,12 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         int64_t x = (int64_t)((ac * (int64_t)d->tup_inv[t][0]) % s1) * d->tup_Mi[t][0];
         for (int g = 0; g < G; ++g) {
             const int jj = d->tup_j[t][g];
-            const int32_t* hb = Hoffall + (size_t)(jj * Q + b) * (s1 + 1);
-            const int cg = min(depth, hb[ac + 1] - hb[ac]);
+            const int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
+            int cg = 0;
+            while (cg < depth && cl[cg] >= 0) ++cg;
             const int ch = r % cg;
             r /= cg;
-            const int32_t h = Hall[(size_t)(jj * Q + b) * T + hb[ac] + ch];
+            const int32_t h = cl[ch];
             const int pm = d->tup_mod[t][g + 1];
             const int64_t res = h % pm;
             x += ((res * d->tup_inv[t][g + 1]) % pm) * d->tup_Mi[t][g + 1];
@@ -599,6 +757,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         else if (x - Mt >= lo) w = x - Mt;
         else continue;
 
+        // the bins of w in every modulus: values for the median, keys for the vote
         float er[kMaxK], ei[kMaxK];
         int votes = 0;                 // heavy bins among the moduli outside tuple t
         const int t_lo = t * G, t_hi = t_lo + G;
@@ -608,14 +767,12 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 const int Pj = d->P[jj];
                 const int hh = (int)pos_mod(w, Pj);
                 const int cls = hh & (s1 - 1);
-                const int32_t* hb = Hoffall + (size_t)(jj * Q + b) * (s1 + 1);
-                const int32_t* Hb = Hall + (size_t)(jj * Q + b) * T;
-                const int e0 = hb[cls], e1 = hb[cls + 1];
-                bool hit = false;
-                for (int e = e0; e < e1; ++e) hit |= (Hb[e] == hh);
-                votes += (hit && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
                 const int k2 = hh % d->p[jj];
                 const float2 ev = Eall[(size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) + cls];
+                const float m2 = fmaf(ev.x, ev.x, ev.y * ev.y);
+                const uint64_t key = ((uint64_t)__float_as_uint(m2) << 32) | (uint64_t)(0xffffffffu - (uint32_t)hh);
+                const bool heavy = key >= thr[jj * Q + b];
+                votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
                 er[jj] = ev.x;
                 ei[jj] = ev.y;
             }
@@ -812,14 +969,15 @@ int select_blocks(const SigDesc& d) { return d.K * d.Q; }
 
 size_t rows_lds_bytes(const SigDesc& d) {
     const int rows_per = std::max(1, kRowElems >> d.log2s1);
-    return (size_t)rows_per * d.s1 * 8;
+    return (size_t)rows_per * d.s1 * 8 + (size_t)(d.s1 / 2) * 8 + 64;
 }
 size_t cols_lds_bytes(const SigDesc& d) {
     int pmax = 0;
     for (int j = 0; j < d.K; ++j) pmax = std::max(pmax, d.p[j]);
-    return (size_t)pmax * std::min(kColChunk, d.s1) * 8;
+    const size_t h = (size_t)(pmax - 1) / 2;
+    return (size_t)pmax * std::min(kColChunk, d.s1) * 8 + h * h * 8 + 64;
 }
-size_t select_lds_bytes(const SigDesc& d) { return (size_t)d.Tpow2 * 12 + 256 * 4 + 64; }
+size_t select_lds_bytes(const SigDesc&) { return 256 * 4 + 64; }
 
 // Dynamic LDS above 64 KiB: raise each kernel's limit where the runtime asks
 // for an opt-in.  A rejected request is not an error here: the launch itself
@@ -837,13 +995,17 @@ hipError_t configure_kernels(int max_lds) {
     return hipSuccess;
 }
 
-hipError_t launch_gather(const BatchArgs& a, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(kThreads), 0, st, a);
+hipError_t launch_gather(const BatchArgs& a, int blocks, int taps, hipStream_t st) {
+    switch (taps) {
+        case 9: hipLaunchKernelGGL(k_gather<9>, dim3(blocks), dim3(kThreads), 0, st, a); break;
+        case 13: hipLaunchKernelGGL(k_gather<13>, dim3(blocks), dim3(kThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_gather<0>, dim3(blocks), dim3(kThreads), 0, st, a); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_dft(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(k_dft, dim3(blocks), dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL(k_dft, dim3(blocks), dim3(kDftThreads), lds, st, a);
     return hipGetLastError();
 }
 

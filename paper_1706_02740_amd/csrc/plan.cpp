@@ -202,12 +202,13 @@ WorkspaceLayout workspace_layout(const sft_plan_info& in) {
     w.S = align256(QM * 8);
     w.E = align256(QM * 8);
     w.H = align256((size_t)in.K * in.Q * in.T * 4);
-    w.Hoff = align256((size_t)in.K * in.Q * (in.s1 + 1) * 4);
+    w.thr = align256((size_t)in.K * in.Q * 8);
+    w.CL = align256((size_t)in.K * in.Q * in.s1 * in.depth * 4);
     w.Rw = align256((size_t)in.Q * in.s * 8);
     w.Rv = align256((size_t)in.Q * in.s * 16);
     w.Rn = align256((size_t)in.Q * 4);
     w.status = 256;
-    w.total = w.S + w.E + w.H + w.Hoff + w.Rw + w.Rv + w.Rn + w.status;
+    w.total = w.S + w.E + w.H + w.thr + w.CL + w.Rw + w.Rv + w.Rn + w.status;
     return w;
 }
 
@@ -215,8 +216,9 @@ size_t dft_lds_bytes(const SigDesc& d) {
     int32_t Pmax = 0;
     for (int j = 0; j < d.K; ++j)
         if (d.P[j] > Pmax) Pmax = d.P[j];
-    // keys / data (8 B per bin) + sort buffer (class + key, 12 B) + histogram
-    return (size_t)Pmax * 8 + (size_t)d.Tpow2 * 12 + 256 * 4 + 64;
+    const size_t h = (size_t)(d.p[d.K - 1] - 1) / 2;
+    // data / keys (8 B per bin) + s1/2 twiddles + h^2 cos/sin pairs + histogram + scan partials
+    return (size_t)Pmax * 8 + (size_t)(d.s1 / 2) * 8 + h * h * 8 + 256 * 4 + 64;
 }
 
 }  // namespace sft

@@ -10,12 +10,14 @@ namespace sft {
 
 constexpr int kMaxK = SFT_MAX_MODULI;
 constexpr int kMaxG = 7;
-constexpr int kThreads = 256;          // every kernel runs 256-thread workgroups (4 wave64)
+constexpr int kThreads = 256;          // workgroup size of every kernel but k_dft (4 wave64)
+constexpr int kDftThreads = 512;       // k_dft workgroup size (8 wave64)
 constexpr int kBandChunk = 16;         // bands accumulated per pass of the gather kernel
 constexpr int kAcceptCap = 4096;       // accepted candidates per band kept in LDS
 constexpr int kMergeCap = 4096;        // band results merged per signal in LDS
 constexpr int kRowElems = 4096;        // complex values per workgroup in the split path's row FFTs
 constexpr int kColChunk = 64;          // columns per workgroup in the split path's p-point DFTs
+constexpr int kMaxDepth = 8;           // class-list length bound (depth^G <= 64 with G >= 2)
 
 // Status bits written by the device.
 constexpr int kStatusAcceptOverflow = 1;
@@ -62,8 +64,9 @@ struct IoDesc {
     int32_t* out_n;
     float2* S;        // [Q*M] filtered samples
     float2* E;        // [Q*M] short-DFT bins
-    int32_t* H;       // [K*Q*T] heavy bins
-    int32_t* Hoff;    // [K*Q*(s1+1)] class offsets into H
+    int32_t* H;       // [K*Q*T] heavy bins, ascending Good-Thomas position (for inspection)
+    uint64_t* thr;    // [K*Q] selection threshold: a bin is heavy iff its key >= thr
+    int32_t* CL;      // [K*Q*s1*depth] per residue class: heaviest heavy bins, -1 padded
     int64_t* Rw;      // [Q*s] band results: frequencies
     double2* Rv;      // [Q*s] band results: coefficients
     int32_t* Rn;      // [Q] band result counts
@@ -82,7 +85,7 @@ struct BatchArgs {
 
 // Per-signal workspace sizes in bytes (each slice 256-byte aligned).
 struct WorkspaceLayout {
-    size_t S, E, H, Hoff, Rw, Rv, Rn, status, total;
+    size_t S, E, H, thr, CL, Rw, Rv, Rn, status, total;
 };
 
 // plan.cpp
@@ -96,7 +99,8 @@ int gather_blocks(const SigDesc& d);
 int dft_blocks(const SigDesc& d);
 int identify_blocks(const SigDesc& d);
 int merge_blocks(const SigDesc& d);
-hipError_t launch_gather(const BatchArgs& a, int blocks, hipStream_t st);
+// taps: 2 kappa + 1 shared by every transform of the launch, or 0 (read per transform)
+hipError_t launch_gather(const BatchArgs& a, int blocks, int taps, hipStream_t st);
 hipError_t launch_dft(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 // split short-DFT path for blocks larger than one workgroup's LDS

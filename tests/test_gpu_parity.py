@@ -169,12 +169,16 @@ def test_prime_n10000019_s128_40db(gpu):
 
 
 def test_batched_equals_plain_mixed_plans(gpu):
-    shapes = [(2 ** 14, 8), (100_003, 20), (2 ** 16, 40), (2 ** 14, 8), (31, 1), (3 * 2 ** 15, 12)]
+    """One execute_many over transforms of different N, s and window widths
+    (13- and 9-tap plans together run the generic gather kernel) equals the
+    single-transform calls (which run the compile-time-tap kernels) bit for bit."""
+    shapes = [(2 ** 14, 8, 0), (100_003, 20, 0), (2 ** 16, 40, 1), (2 ** 14, 8, 0), (31, 1, 0),
+              (3 * 2 ** 15, 12, 1), (2 ** 14, 8, 2)]
     plans = {}
-    for N, s in shapes:
-        if (N, s) not in plans:
-            plans[(N, s)] = gpu.Plan(N, s)
-    sigs = [siggen.sparse_signal(N, s, seed=50 + i, snr_db=30.0) for i, (N, s) in enumerate(shapes)]
+    for N, s, pr in shapes:
+        if (N, s, pr) not in plans:
+            plans[(N, s, pr)] = gpu.Plan(N, s, preset=pr)
+    sigs = [siggen.sparse_signal(N, s, seed=50 + i, snr_db=30.0) for i, (N, s, _) in enumerate(shapes)]
     fs = [dev(sg.f32) for sg in sigs]
     pl = [plans[sh] for sh in shapes]
     say("batched mixed", len(shapes))
