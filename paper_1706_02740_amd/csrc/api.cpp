@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -130,7 +131,12 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         delete pl;
         return fail(SFT_EINVAL, "dft_path must be 0, 1 or 2");
     }
-    pl->split = path == 2 || (path == 0 && dft_lds_bytes(d) > lds_cap);
+    const bool fits = dft_fits_one_workgroup(d) && dft_lds_bytes(d) <= lds_cap;
+    if (path == 1 && !fits) {
+        delete pl;
+        return fail(SFT_EUNSUPPORTED, "the in-LDS short-DFT kernel cannot hold this plan (use dft_path 0 or 2)");
+    }
+    pl->split = path == 2 || (path == 0 && !fits);
     pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
     pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d);
     pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
@@ -138,7 +144,8 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);
     pl->blocks[SFT_KERNEL_MERGE] = merge_blocks(d);
     if (!pl->split) {
-        pl->lds[SFT_KERNEL_DFT] = dft_lds_bytes(d);
+        // low 32 bits: LDS bytes; above: output pairs per thread (selects the kernel variant)
+        pl->lds[SFT_KERNEL_DFT] = dft_lds_bytes(d) | ((size_t)dft_pairs_per_thread(d) << 32);
         pl->blocks[SFT_KERNEL_DFT] = dft_blocks(d);
     } else {
         pl->lds[SFT_KERNEL_DFT_ROWS] = rows_lds_bytes(d);
@@ -149,7 +156,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         pl->blocks[SFT_KERNEL_SELECT] = select_blocks(d);
     }
     for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
-        if (k != SFT_KERNEL_GATHER && pl->lds[k] > lds_cap) {
+        if (k != SFT_KERNEL_GATHER && (pl->lds[k] & 0xffffffffu) > lds_cap) {
             delete pl;
             return fail(SFT_EUNSUPPORTED, "plan needs more LDS per workgroup than the device holds");
         }
@@ -161,7 +168,10 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     const size_t n_tws1 = d.s1 >= 2 ? (size_t)d.s1 / 2 : 1;
     size_t n_twp = 0;
     for (int j = 0; j < d.K; ++j) n_twp += d.p[j];
-    std::vector<float2> band(n_band), tws1(n_tws1), twp(n_twp);
+    size_t n_trig = 0;
+    for (int j = 0; j < d.K; ++j) n_trig += (size_t)((d.p[j] - 1) / 2) * ((d.p[j] - 1) / 2);
+    if (n_trig == 0) n_trig = 1;
+    std::vector<float2> band(n_band), tws1(n_tws1), twp(n_twp), trig(n_trig);
     std::vector<float> rate(d.Q);
     for (int b = 0; b < d.Q; ++b) {
         const int64_t q = info.q_first + 2 * (int64_t)b * info.L;
@@ -184,9 +194,19 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
             const double ang = -2.0 * M_PI * (double)m / (double)d.p[j];
             twp[o] = make_float2((float)cos(ang), (float)sin(ang));
         }
+    o = 0;
+    for (int j = 0; j < d.K; ++j) {
+        const int pj = d.p[j], hj = (pj - 1) / 2;
+        for (int n = 1; n <= hj; ++n)
+            for (int k = 1; k <= hj; ++k, ++o) {
+                const double ang = 2.0 * M_PI * (double)((n * k) % pj) / (double)pj;
+                trig[o] = make_float2((float)cos(ang), (float)sin(ang));
+            }
+    }
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al(d.Q * 4);
-    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate;
+    const size_t b_trig = al(n_trig * 8);
+    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig;
     hipError_t e = hipMalloc(&pl->tables, tbytes);
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(tables) failed"); }
     char* tb = static_cast<char*>(pl->tables);
@@ -194,10 +214,13 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     d.tw_s1 = reinterpret_cast<const float2*>(tb + b_band);
     d.tw_p = reinterpret_cast<const float2*>(tb + b_band + b_tws1);
     d.rate = reinterpret_cast<const float*>(tb + b_band + b_tws1 + b_twp);
+    d.trig = reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate);
     e = hipMemcpy(tb, band.data(), n_band * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band, tws1.data(), n_tws1 * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1, twp.data(), n_twp * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1 + b_twp, rate.data(), d.Q * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate, trig.data(), n_trig * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(tables)"); }
     e = hipMalloc(&pl->ddesc, sizeof(SigDesc));
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(descriptor) failed"); }
@@ -420,7 +443,11 @@ int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* 
         wsoff[i] = ws_total;
         ws_total += p->wl.total;
         for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
-            if (k != SFT_KERNEL_GATHER && p->lds[k] > lds[k]) lds[k] = p->lds[k];
+            if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes)
+                const size_t hi = std::max(p->lds[k] >> 32, lds[k] >> 32);
+                const size_t lo = std::max(p->lds[k] & 0xffffffffu, lds[k] & 0xffffffffu);
+                lds[k] = (hi << 32) | lo;
+            }
         // one compile-time tap count when every transform shares it, else the generic kernel
         if (i == 0) lds[SFT_KERNEL_GATHER] = p->lds[SFT_KERNEL_GATHER];
         else if (lds[SFT_KERNEL_GATHER] != p->lds[SFT_KERNEL_GATHER]) lds[SFT_KERNEL_GATHER] = 0;

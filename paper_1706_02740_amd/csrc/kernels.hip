@@ -303,27 +303,51 @@ __device__ void fft_rows_lds(float2* buf, int rows, int s1, int lg, const float2
     }
 }
 
-// Cosine/sine table of the p-point step: trig[(n - 1) h + (k - 1)] =
-// (cos, sin)(2 pi (n k mod p) / p) for n, k in [1, h], h = (p - 1) / 2, built in
-// LDS from the plan's exp(-2 pi i m / p) table.
+// Cosine/sine table of a p-point step (host-computed per modulus), copied to
+// LDS: trig[(n - 1) h + (k - 1)] = (cos, sin)(2 pi (n k mod p) / p), n, k in [1, h].
 template <int NT>
-__device__ void build_trig(float2* trig, int p, const float2* __restrict__ twp) {
-    const int h = (p - 1) >> 1;
-    for (int i = (int)threadIdx.x; i < h * h; i += NT) {
-        const int n = i / h + 1;
-        const int k = i - (n - 1) * h + 1;
-        const float2 w = twp[(n * k) % p];
-        trig[i] = make_float2(w.x, -w.y);
+__device__ void load_trig(float2* trig, int h, const float2* __restrict__ src) {
+    for (int i = (int)threadIdx.x; i < h * h; i += NT) trig[i] = src[i];
+}
+
+constexpr int kDftKB = 8;       // output pairs per work item, split path
+
+// One p-point output group of column c: with h = (p - 1) / 2, a_n = x_n + x_{p-n},
+// b_n = x_n - x_{p-n}, C_k = sum_n a_n cos(2 pi n k / p), D_k = sum_n b_n sin(...),
+//   X_k = x_0 + C_k - i D_k,  X_{p-k} = x_0 + C_k + i D_k,  X_0 = x_0 + sum_n a_n.
+// Accumulates C, D for k = k0 .. k0 + KB - 1 (k <= h) and sa = sum_n a_n.
+template <int KBMAX>
+__device__ __forceinline__ void pfa_column_sums(const float2* blk, int stride, int c, int p, int h, int k0, int KB,
+                                                const float2* trig, float2* C, float2* D, float2& sa) {
+#pragma unroll
+    for (int kk = 0; kk < KBMAX; ++kk) {
+        C[kk] = make_float2(0.f, 0.f);
+        D[kk] = make_float2(0.f, 0.f);
+    }
+    sa = make_float2(0.f, 0.f);
+    for (int n = 1; n <= h; ++n) {
+        const float2 xa = blk[n * stride + c];
+        const float2 xb = blk[(p - n) * stride + c];
+        const float2 av = make_float2(xa.x + xb.x, xa.y + xb.y);
+        const float2 bv = make_float2(xa.x - xb.x, xa.y - xb.y);
+        sa.x += av.x;
+        sa.y += av.y;
+        const float2* tr = trig + (n - 1) * h + (k0 - 1);
+#pragma unroll
+        for (int kk = 0; kk < KBMAX; ++kk) {
+            if (kk < KB && k0 + kk <= h) {
+                const float2 t = tr[kk];
+                C[kk].x = fmaf(av.x, t.x, C[kk].x);
+                C[kk].y = fmaf(av.y, t.x, C[kk].y);
+                D[kk].x = fmaf(bv.x, t.y, D[kk].x);
+                D[kk].y = fmaf(bv.y, t.y, D[kk].y);
+            }
+        }
     }
 }
 
-constexpr int kDftKB = 8;   // output pairs (k, p - k) per work item of the p-point step
-
-// p-point DFTs of the columns of a [p][stride] block (LDS), one work item per
-// (column, group of kDftKB output pairs); results scaled by `scale` and written
-// to out[k * out_stride + column].  With h = (p - 1) / 2, a_n = x_n + x_{p-n},
-// b_n = x_n - x_{p-n}, C_k = sum_n a_n cos(2 pi n k / p), D_k = sum_n b_n sin(...):
-//   X_k = x_0 + C_k - i D_k,  X_{p-k} = x_0 + C_k + i D_k,  X_0 = x_0 + sum_n a_n.
+// Split path: p-point DFTs of the columns of a [p][stride] LDS block, one work
+// item per (column, group of kDftKB output pairs), written to out[k * out_stride + c].
 template <int NT>
 __device__ void dft_cols_lds(const float2* blk, int stride, int ncols, int p, const float2* trig,
                              float2* __restrict__ out, int out_stride, float scale) {
@@ -335,32 +359,8 @@ __device__ void dft_cols_lds(const float2* blk, int stride, int ncols, int p, co
         const int c = item - g * ncols;
         const int k0 = 1 + g * kDftKB;
         const float2 x0 = blk[c];
-        float2 C[kDftKB], D[kDftKB];
-#pragma unroll
-        for (int kk = 0; kk < kDftKB; ++kk) {
-            C[kk] = make_float2(0.f, 0.f);
-            D[kk] = make_float2(0.f, 0.f);
-        }
-        float2 sa = make_float2(0.f, 0.f);
-        for (int n = 1; n <= h; ++n) {
-            const float2 xa = blk[n * stride + c];
-            const float2 xb = blk[(p - n) * stride + c];
-            const float2 av = make_float2(xa.x + xb.x, xa.y + xb.y);
-            const float2 bv = make_float2(xa.x - xb.x, xa.y - xb.y);
-            sa.x += av.x;
-            sa.y += av.y;
-            const float2* tr = trig + (n - 1) * h + (k0 - 1);
-#pragma unroll
-            for (int kk = 0; kk < kDftKB; ++kk) {
-                if (k0 + kk <= h) {
-                    const float2 t = tr[kk];
-                    C[kk].x = fmaf(av.x, t.x, C[kk].x);
-                    C[kk].y = fmaf(av.y, t.x, C[kk].y);
-                    D[kk].x = fmaf(bv.x, t.y, D[kk].x);
-                    D[kk].y = fmaf(bv.y, t.y, D[kk].y);
-                }
-            }
-        }
+        float2 C[kDftKB], D[kDftKB], sa;
+        pfa_column_sums<kDftKB>(blk, stride, c, p, h, k0, kDftKB, trig, C, D, sa);
 #pragma unroll
         for (int kk = 0; kk < kDftKB; ++kk) {
             const int k = k0 + kk;
@@ -375,63 +375,87 @@ __device__ void dft_cols_lds(const float2* blk, int stride, int ncols, int p, co
     }
 }
 
-__device__ __forceinline__ uint64_t bin_key(float2 e, int i, int lg, int s1, int P, int64_t cA, int64_t cB) {
+// Selection key of bin h with value e: (bits(|E|^2) << 32) | (2^32 - 1 - h).
+__device__ __forceinline__ uint64_t value_key(float2 e, uint32_t h) {
     const float m2 = fmaf(e.x, e.x, e.y * e.y);
-    const int k2 = i >> lg;
-    const int k1 = i & (s1 - 1);
-    const uint32_t h = (uint32_t)(((int64_t)k1 * cA + (int64_t)k2 * cB) % P);
     return ((uint64_t)__float_as_uint(m2) << 32) | (uint64_t)(0xffffffffu - h);
 }
 
+// Bin index h of Good-Thomas position i = k2 s1 + k1: h = k1 (mod s1), h = k2 (mod p).
+__device__ __forceinline__ uint32_t pfa_bin(int i, int lg, int s1, uint32_t P, uint32_t cA, uint32_t cB) {
+    const uint32_t k2 = (uint32_t)(i >> lg);
+    const uint32_t k1 = (uint32_t)(i & (s1 - 1));
+    return (k1 * cA + k2 * cB) % P;
+}
+
 // The T-th largest of the P distinct keys key(i), 1 <= T: a radix select over
-// 8-bit digits from the most significant one, which stops as soon as the
-// chosen digit's bucket holds exactly the keys still needed.  The keys >= the
-// returned value are exactly the T largest.  hist: LDS int32[256]; part: LDS
-// int32[4].  The digit search is a wave-shuffle scan of the 256 buckets.
+// 10-bit digits from bit 62 down (bit 63 is the sign of |E|^2, always 0), which
+// stops as soon as the chosen digit's bucket holds exactly the keys still
+// needed.  The keys >= the returned value are exactly the T largest.  The
+// digit search is a block scan of the buckets in descending order.
+// hist: LDS int32[kSelBins]; part: LDS int32[NT / 64].
+constexpr int kSelBits = 10;
+static_assert(kSelBins == 1 << kSelBits, "bucket count");
+
 template <int NT, class KeyF>
 __device__ uint64_t kth_largest(KeyF key, int P, int T, int32_t* hist, int32_t* part) {
     __shared__ int32_t sh_digit, sh_need, sh_done;
+    constexpr int BPT = kSelBins / NT;   // buckets per thread
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
     if (T >= P) return 0;
-    uint64_t prefix = 0, pmask = 0;
+    uint64_t prefix = 0, pmask = (uint64_t)1 << 63;
     int need = T;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int i = tid; i < 256; i += NT) hist[i] = 0;
+    int top = 63;   // bits [shift, top) form the next digit
+    for (;;) {
+        const int width = top < kSelBits ? top : kSelBits;
+        const int shift = top - width;
+        const uint64_t dmask = ((uint64_t)1 << width) - 1;
+        for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
         __syncthreads();
         for (int i = tid; i < P; i += NT) {
             const uint64_t k = key(i);
-            if ((k & pmask) == prefix) atomicAdd(&hist[(int)((k >> shift) & 255u)], 1);
+            if ((k & pmask) == prefix) atomicAdd(&hist[(int)((k >> shift) & dmask)], 1);
         }
         __syncthreads();
-        int c = 0, x = 0;
-        if (tid < 256) {   // bucket 255 - tid: a descending suffix count
-            c = hist[255 - tid];
-            x = c;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int y = __shfl_up(x, off);
-                if (lane >= off) x += y;
-            }
-            if (lane == 63) part[wid] = x;
+        const int nb = 1 << width;
+        int cnt[BPT];
+        int loc = 0;
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {   // descending rank r <-> digit nb - 1 - r
+            const int r = tid * BPT + q;
+            cnt[q] = r < nb ? hist[nb - 1 - r] : 0;
+            loc += cnt[q];
         }
+        int x = loc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) part[wid] = x;
         __syncthreads();
-        if (tid < 256) {
-            int base = 0;
-            for (int w = 0; w < wid; ++w) base += part[w];
-            const int incl = base + x;
-            const int excl = incl - c;
-            if (excl < need && incl >= need) {
-                sh_digit = 255 - tid;
-                sh_need = need - excl;
-                sh_done = (c == need - excl) ? 1 : 0;
+        int base = 0;
+        for (int w = 0; w < wid; ++w) base += part[w];
+        const int incl = base + x;
+        int run = incl - loc;
+        if (run < need && incl >= need) {
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                if (run < need && run + cnt[q] >= need) {
+                    sh_digit = nb - 1 - (tid * BPT + q);
+                    sh_need = need - run;
+                    sh_done = (cnt[q] == need - run) ? 1 : 0;
+                }
+                run += cnt[q];
             }
         }
         __syncthreads();
         prefix |= (uint64_t)sh_digit << shift;
-        pmask |= (uint64_t)255u << shift;
+        pmask |= dmask << shift;
         need = sh_need;
-        if (sh_done) break;   // sh_* change again only after the next pass's second barrier
+        if (sh_done || shift == 0) break;   // sh_* change again only after the next pass's third barrier
+        top = shift;
     }
     return prefix;
 }
@@ -457,46 +481,62 @@ __device__ int block_exclusive_sum(int v, int32_t* part) {
 
 // Heavy bins of one block (keys >= thr).  Writes the threshold, the heavy bins
 // in ascending Good-Thomas position (H[T]), and for every residue class c mod
-// s1, which is column c of the [p][s1] layout, the `depth` heaviest heavy bins
-// of the class in descending key order (CL[c * depth + e], -1 where fewer).
+// s1 (column c of the [p][s1] layout) the `depth` heaviest heavy bins of the
+// class in descending key order (CL[c * depth + e], -1 where fewer).  The T
+// heavy keys are gathered once into hk (LDS, T entries); each one's position
+// rank and class rank then come from a scan of hk that every lane reads in
+// the same order (LDS broadcast).  CL must be writable by this workgroup only.
 template <int NT, class KeyF>
-__device__ void emit_heavy(KeyF key, int P, int s1, int p, int depth, uint64_t thr, int32_t* part,
+__device__ void emit_heavy(KeyF key, int P, int T, int s1, int lg, int depth, uint64_t thr, uint64_t* hk,
                            int32_t* __restrict__ H, uint64_t* __restrict__ thr_out, int32_t* __restrict__ CL) {
+    __shared__ int32_t sh_n;
     const int tid = (int)threadIdx.x;
-    if (tid == 0) *thr_out = thr;
-    for (int c = tid; c < s1; c += NT) {
-        uint64_t top[kMaxDepth];
-#pragma unroll
-        for (int e = 0; e < kMaxDepth; ++e) top[e] = 0;   // every real key is > 0
-        for (int k2 = 0; k2 < p; ++k2) {
-            uint64_t k = key(k2 * s1 + c);
-            if (k >= thr) {
-#pragma unroll
-                for (int e = 0; e < kMaxDepth; ++e) {
-                    if (e < depth && k > top[e]) {
-                        const uint64_t t = top[e];
-                        top[e] = k;
-                        k = t;
-                    }
-                }
+    if (tid == 0) {
+        *thr_out = thr;
+        sh_n = 0;
+    }
+    for (int i = tid; i < s1 * depth; i += NT) CL[i] = -1;
+    __syncthreads();
+    // keys carry h in their low half; the position is recovered from the bin
+    // below, so hk holds (key, position) pairs packed as key with the position
+    // in a parallel slot: hk[2e] = key, hk[2e + 1] = position.
+    for (int i = tid; i < P; i += NT) {
+        const uint64_t k = key(i);
+        if (k >= thr) {
+            const int e = atomicAdd(&sh_n, 1);
+            if (e < T) {
+                hk[2 * e] = k;
+                hk[2 * e + 1] = (uint64_t)i;
             }
         }
-        for (int e = 0; e < depth; ++e)
-            CL[c * depth + e] = top[e] ? (int32_t)(0xffffffffu - (uint32_t)(top[e] & 0xffffffffu)) : -1;
     }
-    const int chunk = (P + NT - 1) / NT;
-    const int beg = min(P, tid * chunk);
-    const int end = min(P, beg + chunk);
-    int mine = 0;
-    for (int i = beg; i < end; ++i) mine += key(i) >= thr ? 1 : 0;
-    int o = block_exclusive_sum<NT>(mine, part);
-    for (int i = beg; i < end; ++i) {
-        const uint64_t k = key(i);
-        if (k >= thr) H[o++] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+    __syncthreads();
+    const int n = min(sh_n, T);
+    for (int e = tid; e < n; e += NT) {
+        const uint64_t k = hk[2 * e];
+        const int pos = (int)hk[2 * e + 1];
+        const uint32_t h = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
+        const int cls = pos & (s1 - 1);   // = h mod s1
+        int before = 0, heavier = 0;
+        for (int f = 0; f < n; ++f) {
+            const uint64_t kf = hk[2 * f];
+            const int pf = (int)hk[2 * f + 1];
+            before += pf < pos ? 1 : 0;
+            heavier += ((pf & (s1 - 1)) == cls && kf > k) ? 1 : 0;
+        }
+        H[before] = (int32_t)h;
+        if (heavier < depth) CL[cls * depth + heavier] = (int32_t)h;
     }
+    (void)lg;
 }
 
-// One workgroup per (modulus j, band b); the whole block in LDS.
+// One workgroup per (modulus j, band b); the whole block in LDS.  Requires
+// s1 <= kDftThreads and ceil(h / (kDftThreads / s1)) <= KBMAX, h = (p-1)/2
+// (KBMAX = 8 keeps two workgroups per CU; 16 serves s1 = 256).
+// Step B runs one work item per thread (output group g = tid / s1 of column
+// c = tid mod s1); the results stay in registers across a barrier and are then
+// written to E, while their selection keys overwrite the LDS block.
+template <int KBMAX>
 __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = kDftThreads;
@@ -514,6 +554,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const int lg = d->log2s1;
     const int Pmax = d->P[K - 1];
     const int hmax = (d->p[K - 1] - 1) >> 1;
+    const int h = (p - 1) >> 1;
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
 
     float2* buf = reinterpret_cast<float2*>(smem);
@@ -521,27 +562,54 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     float2* tw = reinterpret_cast<float2*>(smem + (size_t)Pmax * 8);
     float2* trig = tw + (s1 >> 1);
     int32_t* hist = reinterpret_cast<int32_t*>(trig + hmax * hmax);
-    int32_t* part = hist + 256;
+    int32_t* part = hist + kSelBins;
+    uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [2 T]
 
     const float2* __restrict__ S = io.S + base;
     for (int i = tid; i < P; i += NT) buf[i] = S[i];
     for (int i = tid; i < (s1 >> 1); i += NT) tw[i] = d->tw_s1[i];
-    build_trig<NT>(trig, p, d->tw_p + d->tw_off[j]);
+    load_trig<NT>(trig, h, d->trig + d->trig_off[j]);
     __syncthreads();
     fft_rows_lds<NT>(buf, p, s1, lg, tw);
 
-    // step B; the keys below re-read E: same workgroup, ordered by the barrier
+    // step B
+    const int ng = NT >> lg;
+    const int KB = (h + ng - 1) / ng;
+    const int g = tid >> lg;
+    const int c = tid & (s1 - 1);
+    const int k0 = 1 + g * KB;
+    const float2 x0 = buf[c];
+    float2 C[KBMAX], D[KBMAX], sa;
+    pfa_column_sums<KBMAX>(buf, s1, c, p, h, k0, KB, trig, C, D, sa);
+    __syncthreads();   // every column has been read: the block may be overwritten
     float2* __restrict__ E = io.E + base;
-    dft_cols_lds<NT>(buf, s1, s1, p, trig, E, s1, 1.0f / (float)P);
-    __syncthreads();
-    const int64_t cA = (int64_t)p * d->pinv_s1[j];
-    const int64_t cB = (int64_t)s1 * d->s1inv_p[j];
-    for (int i = tid; i < P; i += NT) keys[i] = bin_key(E[i], i, lg, s1, P, cA, cB);
+    const float scale = 1.0f / (float)P;
+    const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
+    const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
+#pragma unroll
+    for (int kk = 0; kk < KBMAX; ++kk) {
+        const int k = k0 + kk;
+        if (kk < KB && k <= h) {
+            const float2 xk = make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale);
+            const float2 xm = make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale);
+            const int ik = (k << lg) + c;
+            const int im = ((p - k) << lg) + c;
+            E[ik] = xk;
+            E[im] = xm;
+            keys[ik] = value_key(xk, pfa_bin(ik, lg, s1, (uint32_t)P, cA, cB));
+            keys[im] = value_key(xm, pfa_bin(im, lg, s1, (uint32_t)P, cA, cB));
+        }
+    }
+    if (g == 0) {
+        const float2 xz = make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale);
+        E[c] = xz;
+        keys[c] = value_key(xz, pfa_bin(c, lg, s1, (uint32_t)P, cA, cB));
+    }
     __syncthreads();
     auto kf = [&](int i) { return keys[i]; };
     const uint64_t thr = kth_largest<NT>(kf, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<NT>(kf, P, s1, p, d->depth, thr, part, io.H + blk * d->T, io.thr + blk,
+    emit_heavy<NT>(kf, P, d->T, s1, lg, d->depth, thr, hk, io.H + blk * d->T, io.thr + blk,
                    io.CL + blk * (size_t)s1 * d->depth);
 }
 
@@ -618,7 +686,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
         const int k1 = c0 + (i - n2 * C);
         tile[i] = E[((size_t)n2 << lg) + k1];
     }
-    build_trig<kThreads>(trig, p, d->tw_p + d->tw_off[j]);
+    load_trig<kThreads>(trig, (p - 1) >> 1, d->trig + d->trig_off[j]);
     __syncthreads();
     dft_cols_lds<kThreads>(tile, C, C, p, trig, E + c0, s1, 1.0f / (float)P);
 }
@@ -637,14 +705,15 @@ __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
     const int s1 = d->s1;
     const int lg = d->log2s1;
     int32_t* hist = reinterpret_cast<int32_t*>(smem);
-    int32_t* part = hist + 256;
+    int32_t* part = hist + kSelBins;
+    uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [2 T]
     const float2* __restrict__ E = io.E + (size_t)Q * d->Moff[j] + (size_t)b * P;
-    const int64_t cA = (int64_t)p * d->pinv_s1[j];
-    const int64_t cB = (int64_t)s1 * d->s1inv_p[j];
-    auto kf = [&](int i) { return bin_key(E[i], i, lg, s1, P, cA, cB); };
+    const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
+    const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
+    auto kf = [&](int i) { return value_key(E[i], pfa_bin(i, lg, s1, (uint32_t)P, cA, cB)); };
     const uint64_t thr = kth_largest<kThreads>(kf, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<kThreads>(kf, P, s1, p, d->depth, thr, part, io.H + blk * d->T, io.thr + blk,
+    emit_heavy<kThreads>(kf, P, d->T, s1, lg, d->depth, thr, hk, io.H + blk * d->T, io.thr + blk,
                          io.CL + blk * (size_t)s1 * d->depth);
 }
 
@@ -694,30 +763,39 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     const int64_t lo = d->lo, hi = d->hi;
     const int nslots = 2 * s1;
 
+    const int acap = d->accept_cap;
     uint64_t* akey = reinterpret_cast<uint64_t*>(smem);
-    float2* az = reinterpret_cast<float2*>(smem + (size_t)kAcceptCap * 8);
-    int32_t* flag = reinterpret_cast<int32_t*>(smem + (size_t)kAcceptCap * 16);
-    int32_t* scratch = flag + kAcceptCap;
+    float2* az = reinterpret_cast<float2*>(smem + (size_t)acap * 8);
+    int32_t* flag = reinterpret_cast<int32_t*>(smem + (size_t)acap * 16);
+    int32_t* scratch = flag + acap;
     int32_t* pre = scratch + kThreads;
+    uint64_t* thr = reinterpret_cast<uint64_t*>(pre + ((nslots + 2) & ~1));   // [K]
+    uint8_t* ccount = reinterpret_cast<uint8_t*>(thr + kMaxK);                // [K * s1]
     __shared__ int32_t sh_cnt;
 
     const int32_t* __restrict__ CLall = io.CL;
-    const uint64_t* __restrict__ thr = io.thr;
     const float2* __restrict__ Eall = io.E;
     const size_t cl_stride = (size_t)s1 * depth;   // one (modulus, band) block of class lists
+
+    // 0. thresholds and class-list lengths of this band's K blocks, into LDS
+    for (int jj = tid; jj < K; jj += kThreads) thr[jj] = io.thr[jj * Q + b];
+    for (int i = tid; i < K * s1; i += kThreads) {
+        const int jj = i >> lg;
+        const int ac = i & (s1 - 1);
+        const int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
+        int n = 0;
+#pragma unroll
+        for (int e = 0; e < kMaxDepth; ++e) n += (e < depth && cl[e] >= 0) ? 1 : 0;   // lists are -1 padded
+        ccount[i] = (uint8_t)n;
+    }
+    __syncthreads();
 
     // 1. combinations per (tuple, class) slot: product of the class-list lengths
     for (int slot = tid; slot < nslots; slot += kThreads) {
         const int t = slot >> lg;
         const int ac = slot & (s1 - 1);
         int cnt = 1;
-        for (int g = 0; g < G; ++g) {
-            const int jj = d->tup_j[t][g];
-            const int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
-            int n = 0;
-            while (n < depth && cl[n] >= 0) ++n;
-            cnt *= n;
-        }
+        for (int g = 0; g < G; ++g) cnt *= ccount[(d->tup_j[t][g] << lg) + ac];
         pre[slot] = cnt;
     }
     if (tid == 0) sh_cnt = 0;
@@ -741,8 +819,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         for (int g = 0; g < G; ++g) {
             const int jj = d->tup_j[t][g];
             const int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
-            int cg = 0;
-            while (cg < depth && cl[cg] >= 0) ++cg;
+            const int cg = ccount[(jj << lg) + ac];
             const int ch = r % cg;
             r /= cg;
             const int32_t h = cl[ch];
@@ -769,9 +846,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 const int cls = hh & (s1 - 1);
                 const int k2 = hh % d->p[jj];
                 const float2 ev = Eall[(size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) + cls];
-                const float m2 = fmaf(ev.x, ev.x, ev.y * ev.y);
-                const uint64_t key = ((uint64_t)__float_as_uint(m2) << 32) | (uint64_t)(0xffffffffu - (uint32_t)hh);
-                const bool heavy = key >= thr[jj * Q + b];
+                const bool heavy = value_key(ev, (uint32_t)hh) >= thr[jj];
                 votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
                 er[jj] = ev.x;
                 ei[jj] = ev.y;
@@ -782,7 +857,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
             const float zi = median_of(ei, K);
             const float m2 = fmaf(zr, zr, zi * zi);
             const int pos = atomicAdd(&sh_cnt, 1);
-            if (pos < kAcceptCap) {
+            if (pos < acap) {
                 akey[pos] = ((uint64_t)__float_as_uint(m2) << 32) |
                             (uint64_t)(0xffffffffu - (uint32_t)(w - lo));
                 az[pos] = make_float2(zr, zi);
@@ -792,7 +867,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         }
     }
     __syncthreads();
-    const int nacc = min(sh_cnt, kAcceptCap);
+    const int nacc = min(sh_cnt, acap);
     int np2 = 1;
     while (np2 < nacc) np2 <<= 1;
     for (int i = nacc + tid; i < np2; i += kThreads) {
@@ -946,7 +1021,9 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
 // ------------------------------------------------------------ launchers ---
 
 size_t identify_lds_bytes(const SigDesc& d) {
-    return (size_t)kAcceptCap * 20 + (size_t)kThreads * 4 + (size_t)(2 * d.s1 + 1) * 4 + 64;
+    const int nslots = 2 * d.s1;
+    return (size_t)d.accept_cap * 20 + (size_t)kThreads * 4 + (size_t)((nslots + 2) & ~1) * 4 + kMaxK * 8 +
+           (size_t)d.K * d.s1 + 64;
 }
 
 size_t merge_lds_bytes() {
@@ -977,13 +1054,13 @@ size_t cols_lds_bytes(const SigDesc& d) {
     const size_t h = (size_t)(pmax - 1) / 2;
     return (size_t)pmax * std::min(kColChunk, d.s1) * 8 + h * h * 8 + 64;
 }
-size_t select_lds_bytes(const SigDesc&) { return 256 * 4 + 64; }
+size_t select_lds_bytes(const SigDesc& d) { return kSelBins * 4 + 64 + (size_t)d.T * 16 + 64; }
 
 // Dynamic LDS above 64 KiB: raise each kernel's limit where the runtime asks
 // for an opt-in.  A rejected request is not an error here: the launch itself
 // reports a size the device cannot hold.
 hipError_t configure_kernels(int max_lds) {
-    const void* ks[6] = {(const void*)k_dft, (const void*)k_identify, (const void*)k_merge,
+    const void* ks[7] = {(const void*)k_dft<8>, (const void*)k_dft<16>, (const void*)k_identify, (const void*)k_merge,
                          (const void*)k_dft_rows, (const void*)k_dft_cols, (const void*)k_select};
     for (const void* k : ks) {
         hipFuncAttributes fa;
@@ -1005,7 +1082,10 @@ hipError_t launch_gather(const BatchArgs& a, int blocks, int taps, hipStream_t s
 }
 
 hipError_t launch_dft(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(k_dft, dim3(blocks), dim3(kDftThreads), lds, st, a);
+    // lds carries the byte count in its low 32 bits and the output-pair bound above them
+    const size_t bytes = lds & 0xffffffffu;
+    if ((lds >> 32) > 8) hipLaunchKernelGGL(k_dft<16>, dim3(blocks), dim3(kDftThreads), bytes, st, a);
+    else hipLaunchKernelGGL(k_dft<8>, dim3(blocks), dim3(kDftThreads), bytes, st, a);
     return hipGetLastError();
 }
 

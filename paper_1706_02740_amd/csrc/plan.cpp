@@ -103,6 +103,9 @@ int derive_plan(int64_t N, int32_t s, const sft_params* prm, sft_plan_info* out,
         M += out->P[j];
     }
     if (M > ((int64_t)1 << 31) - 1 || s1 > ((int64_t)1 << 24)) { *why = "too many nodes"; return SFT_EUNSUPPORTED; }
+    int64_t Pmax = 0;
+    for (int j = 0; j < K; ++j) Pmax = out->P[j] > Pmax ? out->P[j] : Pmax;
+    if ((uint64_t)s1 * (uint64_t)Pmax >= ((uint64_t)1 << 32)) { *why = "s1 * P_j must stay below 2^32"; return SFT_EUNSUPPORTED; }
     const int64_t T0 = p.heavy_T > 0 ? p.heavy_T : 2 * (int64_t)s;
     const int64_t T = T0 < Pmin ? T0 : Pmin;
     int32_t depth = 1;
@@ -158,13 +161,16 @@ void fill_desc(const sft_plan_info& in, SigDesc* d) {
     d->Tpow2 = tp;
     d->depth = in.depth;
     d->M = (int32_t)in.M;
+    int ac = 256;
+    while (ac < 8 * in.s && ac < kAcceptCap) ac *= 2;
+    d->accept_cap = ac;
     d->inv2sig2 = (float)(1.0 / (2.0 * in.sigma_t * in.sigma_t));
     d->wnorm = (float)(1.0 / (2.0 * M_PI * in.sigma_t));
     d->a_first = (float)((double)in.q_first / (double)in.N);
     d->a_step = (float)(2.0 * (double)in.L / (double)in.N);
     d->c1sq_half = in.c1 * in.c1 / 2.0;
     d->ghat0 = 1.0 / sqrt(2.0 * M_PI);
-    int32_t off = 0, twoff = 0;
+    int32_t off = 0, twoff = 0, trigoff = 0;
     for (int j = 0; j < in.K; ++j) {
         d->p[j] = in.primes[j];
         d->P[j] = (int32_t)in.P[j];
@@ -174,6 +180,8 @@ void fill_desc(const sft_plan_info& in, SigDesc* d) {
         d->s1inv_p[j] = (int32_t)inv_mod(in.s1, in.primes[j]);
         d->tw_off[j] = twoff;
         twoff += in.primes[j];
+        d->trig_off[j] = trigoff;
+        trigoff += ((in.primes[j] - 1) / 2) * ((in.primes[j] - 1) / 2);
     }
     d->Moff[in.K] = off;
     for (int t = 0; t < 2; ++t) {
@@ -218,7 +226,17 @@ size_t dft_lds_bytes(const SigDesc& d) {
         if (d.P[j] > Pmax) Pmax = d.P[j];
     const size_t h = (size_t)(d.p[d.K - 1] - 1) / 2;
     // data / keys (8 B per bin) + s1/2 twiddles + h^2 cos/sin pairs + histogram + scan partials
-    return (size_t)Pmax * 8 + (size_t)(d.s1 / 2) * 8 + h * h * 8 + 256 * 4 + 64;
+    // + the T heavy (key, position) pairs
+    return (size_t)Pmax * 8 + (size_t)(d.s1 / 2) * 8 + h * h * 8 + (size_t)kSelBins * 4 + 64 + (size_t)d.T * 16 + 64;
 }
+
+int dft_pairs_per_thread(const SigDesc& d) {
+    if (d.s1 > kDftThreads) return 1 << 30;
+    const int ng = kDftThreads / d.s1;
+    const int h = (d.p[d.K - 1] - 1) / 2;
+    return (h + ng - 1) / ng;
+}
+
+bool dft_fits_one_workgroup(const SigDesc& d) { return dft_pairs_per_thread(d) <= kDftKBMax; }
 
 }  // namespace sft

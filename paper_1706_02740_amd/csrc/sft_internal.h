@@ -13,11 +13,13 @@ constexpr int kMaxG = 7;
 constexpr int kThreads = 256;          // workgroup size of every kernel but k_dft (4 wave64)
 constexpr int kDftThreads = 512;       // k_dft workgroup size (8 wave64)
 constexpr int kBandChunk = 16;         // bands accumulated per pass of the gather kernel
-constexpr int kAcceptCap = 4096;       // accepted candidates per band kept in LDS
+constexpr int kAcceptCap = 4096;       // bound on the accepted candidates per band kept in LDS
 constexpr int kMergeCap = 4096;        // band results merged per signal in LDS
 constexpr int kRowElems = 4096;        // complex values per workgroup in the split path's row FFTs
 constexpr int kColChunk = 64;          // columns per workgroup in the split path's p-point DFTs
 constexpr int kMaxDepth = 8;           // class-list length bound (depth^G <= 64 with G >= 2)
+constexpr int kSelBins = 1024;         // buckets of one radix-select pass (10-bit digits)
+constexpr int kDftKBMax = 16;          // p-point output pairs per thread in the in-LDS short-DFT kernel
 
 // Status bits written by the device.
 constexpr int kStatusAcceptOverflow = 1;
@@ -31,6 +33,7 @@ struct SigDesc {
     int64_t q_first;        // q_b = q_first + 2 b L
     int64_t lo, hi;         // B = [lo, hi]
     int32_t s, kappa, taps, Q, K, G, s1, log2s1, T, depth, M, Tpow2;
+    int32_t accept_cap;     // accepted candidates one band may hold: min(4096, pow2 >= 8 s)
     float   inv2sig2;       // 1 / (2 sigma_t^2)
     float   wnorm;          // 1 / (2 pi sigma_t): W(v) = wnorm exp(-v^2 inv2sig2)
     float   a_first;        // q_first / N    (per-node band phase rate, in turns)
@@ -54,6 +57,8 @@ struct SigDesc {
     const float2* tw_s1;     // [s1/2]: exp(-2 pi i k / s1)
     const float2* tw_p;      // concatenated [p_j]: exp(-2 pi i m / p_j)
     const float* rate;       // [Q]: q_b / N, the per-node band phase rate in turns
+    const float2* trig;      // concatenated [h_j^2]: (cos, sin)(2 pi (n k mod p_j) / p_j), n, k in [1, h_j]
+    int32_t trig_off[kMaxK];
 };
 
 // Per-transform pointers: input, outputs and workspace slices.
@@ -93,6 +98,8 @@ int derive_plan(int64_t N, int32_t s, const sft_params* p, sft_plan_info* out, c
 void fill_desc(const sft_plan_info& info, SigDesc* d);
 WorkspaceLayout workspace_layout(const sft_plan_info& info);
 size_t dft_lds_bytes(const SigDesc& d);
+bool dft_fits_one_workgroup(const SigDesc& d);   // the in-LDS short-DFT kernel's shape limits
+int dft_pairs_per_thread(const SigDesc& d);
 
 // kernels.hip: host-side launchers (enqueue only).  Block counts per signal:
 int gather_blocks(const SigDesc& d);
