@@ -164,15 +164,16 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
 
     // ---- tables (FP64 on the host, rounded once to FP32)
     const int taps = d.taps;
-    const size_t n_band = (size_t)d.Q * taps;
+    const int Qpad = (d.Q + kBandChunk - 1) / kBandChunk * kBandChunk;   // zero rows up to whole chunks
+    const size_t n_band = (size_t)Qpad * taps;
     const size_t n_tws1 = d.s1 >= 2 ? (size_t)d.s1 / 2 : 1;
     size_t n_twp = 0;
     for (int j = 0; j < d.K; ++j) n_twp += d.p[j];
     size_t n_trig = 0;
     for (int j = 0; j < d.K; ++j) n_trig += (size_t)((d.p[j] - 1) / 2) * ((d.p[j] - 1) / 2);
     if (n_trig == 0) n_trig = 1;
-    std::vector<float2> band(n_band), tws1(n_tws1), twp(n_twp), trig(n_trig);
-    std::vector<float> rate(d.Q);
+    std::vector<float2> band(n_band, make_float2(0.f, 0.f)), tws1(n_tws1), twp(n_twp), trig(n_trig);
+    std::vector<float> rate(Qpad, 0.f);
     for (int b = 0; b < d.Q; ++b) {
         const int64_t q = info.q_first + 2 * (int64_t)b * info.L;
         rate[b] = (float)((double)q / (double)N);
@@ -204,7 +205,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
             }
     }
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al(d.Q * 4);
+    const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al((size_t)Qpad * 4);
     const size_t b_trig = al(n_trig * 8);
     const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig;
     hipError_t e = hipMalloc(&pl->tables, tbytes);
@@ -218,7 +219,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     e = hipMemcpy(tb, band.data(), n_band * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band, tws1.data(), n_tws1 * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1, twp.data(), n_twp * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1 + b_twp, rate.data(), d.Q * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1 + b_twp, rate.data(), (size_t)Qpad * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate, trig.data(), n_trig * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(tables)"); }
@@ -338,13 +339,15 @@ LaunchFn launcher(int k) {
 }
 
 // Enqueue the pipeline.  prefix[k] is the device prefix table of kernel k
-// (batched) or unused (single transform).
+// (batch of several plans), bps[k] the blocks per transform of a one-plan
+// batch; both null for a single transform.
 int enqueue(BatchArgs a, const int blocks[SFT_KERNEL_COUNT], const size_t lds[SFT_KERNEL_COUNT],
-            const int32_t* const prefix[SFT_KERNEL_COUNT], hipStream_t st) {
+            const int32_t* const prefix[SFT_KERNEL_COUNT], hipStream_t st, const int* bps) {
     for (int o = 0; o < SFT_KERNEL_COUNT; ++o) {
         const int k = kOrder[o];
         if (blocks[k] <= 0) continue;
         a.prefix = prefix ? prefix[k] : nullptr;
+        a.bps = bps ? bps[k] : 0;
         LaunchFn fn = launcher(k);
         const hipError_t e = timed(k, st, [&] { return fn(a, blocks[k], lds[k], st); });
         if (e != hipSuccess) return hip_fail(e, kNames[k]);
@@ -420,7 +423,7 @@ int sft_execute(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_dev, void
     a.io_one.out_n = out_count_dev;
     a.nsig = 1;
     plan->last_stream = st;
-    return enqueue(a, plan->blocks, plan->lds, nullptr, st);
+    return enqueue(a, plan->blocks, plan->lds, nullptr, st, nullptr);
 }
 
 int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* f_dev,
@@ -509,12 +512,18 @@ int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* 
     char* dm = static_cast<char*>(ar->meta);
     BatchArgs a;
     memset(&a, 0, sizeof(a));
-    a.descs_many = reinterpret_cast<const SigDesc* const*>(dm);
     a.io_many = reinterpret_cast<const IoDesc*>(dm + m_desc);
     a.nsig = count;
+    bool one_plan = true;
+    for (int i = 1; i < count; ++i) one_plan &= plans[i] == plans[0];
+    if (one_plan) {   // blocks follow from blockIdx by a division; one descriptor
+        a.desc_one = plans[0]->ddesc;
+        return enqueue(a, blocks, lds, nullptr, st, plans[0]->blocks);
+    }
+    a.descs_many = reinterpret_cast<const SigDesc* const*>(dm);
     const int32_t* dpre[SFT_KERNEL_COUNT];
     for (int k = 0; k < SFT_KERNEL_COUNT; ++k) dpre[k] = reinterpret_cast<const int32_t*>(dm + m_desc + m_io + k * m_pre);
-    return enqueue(a, blocks, lds, dpre, st);
+    return enqueue(a, blocks, lds, dpre, st, nullptr);
 }
 
 int sft_plan_status(sft_plan_t plan, int32_t* flags) {

@@ -21,6 +21,48 @@ namespace sft {
 
 // ----------------------------------------------------------------- helpers --
 
+// Pointers read out of descriptors are generic; these casts restore their
+// address space so that wave-uniform reads become scalar (constant) loads and
+// data accesses use global (not flat) instructions.
+#define GLOBAL __attribute__((address_space(1)))
+#define CONSTANT __attribute__((address_space(4)))
+
+template <class T>
+__device__ __forceinline__ const CONSTANT T* cst(const T* p) { return (const CONSTANT T*)(p); }
+template <class T>
+__device__ __forceinline__ const GLOBAL T* glb(const T* p) { return (const GLOBAL T*)(p); }
+template <class T>
+__device__ __forceinline__ GLOBAL T* glb(T* p) { return (GLOBAL T*)(p); }
+
+// float2 / double2 are classes whose copies take generic references: address-
+// space-qualified element accesses go through these POD vector loads/stores.
+typedef float pod_f2 __attribute__((ext_vector_type(2)));
+typedef double pod_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld2(const GLOBAL float2* p) {
+    const pod_f2 v = *(const GLOBAL pod_f2*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld2(const CONSTANT float2* p) {
+    const pod_f2 v = *(const CONSTANT pod_f2*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(GLOBAL float2* p, float2 v) {
+    pod_f2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(GLOBAL pod_f2*)p = w;
+}
+__device__ __forceinline__ double2 ldd2(const GLOBAL double2* p) {
+    const pod_d2 v = *(const GLOBAL pod_d2*)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void std2(GLOBAL double2* p, double2 v) {
+    pod_d2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(GLOBAL pod_d2*)p = w;
+}
+
 struct Where {
     int sig;
     int blk;
@@ -29,27 +71,36 @@ struct Where {
 __device__ __forceinline__ Where locate(const BatchArgs& a) {
     Where w;
     const int b = (int)blockIdx.x;
-    if (a.descs_many == nullptr) {
+    if (a.io_many == nullptr) {
         w.sig = 0;
         w.blk = b;
         return w;
     }
+    if (a.bps > 0) {
+        w.sig = b / a.bps;
+        w.blk = b - w.sig * a.bps;
+        return w;
+    }
+    const CONSTANT int32_t* pre = cst(a.prefix);
     int lo = 0, hi = a.nsig - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (a.prefix[mid] <= b) lo = mid; else hi = mid - 1;
+        if (pre[mid] <= b) lo = mid; else hi = mid - 1;
     }
     w.sig = lo;
-    w.blk = b - a.prefix[lo];
+    w.blk = b - pre[lo];
     return w;
 }
 
-__device__ __forceinline__ const SigDesc* desc_of(const BatchArgs& a, int sig) {
-    return a.descs_many ? a.descs_many[sig] : a.desc_one;
+__device__ __forceinline__ const CONSTANT SigDesc* desc_of(const BatchArgs& a, int sig) {
+    return cst(a.descs_many ? cst(a.descs_many)[sig] : a.desc_one);
 }
 
 __device__ __forceinline__ IoDesc io_of(const BatchArgs& a, int sig) {
-    return a.descs_many ? a.io_many[sig] : a.io_one;
+    if (a.io_many == nullptr) return a.io_one;
+    IoDesc io;
+    __builtin_memcpy(&io, (const IoDesc*)(cst(a.io_many) + sig), sizeof(IoDesc));
+    return io;
 }
 
 __device__ __forceinline__ int64_t pos_mod(int64_t x, int64_t m) {
@@ -100,13 +151,13 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
 
 constexpr int kPhaseAnchor = 8;
 
-__device__ __forceinline__ float tap_weight(int32_t delta, int o, int P, float Pf, float wnorm, float inv2sig2) {
-    const float v = (float)(delta - o * P) / Pf;
+__device__ __forceinline__ float tap_weight(int32_t delta, int o, int P, float invP, float wnorm, float inv2sig2) {
+    const float v = (float)(delta - o * P) * invP;
     return wnorm * expf(-v * v * inv2sig2);
 }
 
-__device__ __forceinline__ void store_bands(float2* __restrict__ S, int P, int b0, int nb, const float2* acc,
-                                            float u, const float* __restrict__ rate, float step_rate) {
+__device__ __forceinline__ void store_bands(GLOBAL float2* __restrict__ S, int P, int b0, int nb, const float2* acc,
+                                            float u, const CONSTANT float* rate, float step_rate) {
     float sn, cs;
     sincospif(2.0f * u * step_rate, &sn, &cs);
     const float2 step = make_float2(cs, sn);
@@ -120,8 +171,8 @@ __device__ __forceinline__ void store_bands(float2* __restrict__ S, int P, int b
             } else {
                 ph = make_float2(ph.x * step.x - ph.y * step.y, ph.x * step.y + ph.y * step.x);
             }
-            S[(size_t)(b0 + bb) * P] = make_float2(acc[bb].x * ph.x - acc[bb].y * ph.y,
-                                                   acc[bb].x * ph.y + acc[bb].y * ph.x);
+            st2(S + (size_t)(b0 + bb) * P, make_float2(acc[bb].x * ph.x - acc[bb].y * ph.y,
+                                                        acc[bb].x * ph.y + acc[bb].y * ph.x));
         }
     }
 }
@@ -129,9 +180,9 @@ __device__ __forceinline__ void store_bands(float2* __restrict__ S, int P, int b
 template <int TAPS>
 __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
     const Where at = locate(a);
-    const SigDesc* __restrict__ d = desc_of(a, at.sig);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
-    if (at.blk == 0 && threadIdx.x == 0) io.status[0] = 0;
+    if (at.blk == 0 && threadIdx.x == 0) glb(io.status)[0] = 0;
     const int g = at.blk * kThreads + (int)threadIdx.x;
     const int M = d->M;
     if (g >= M) return;
@@ -151,14 +202,15 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
     const int32_t delta = (int32_t)(nN - jp * P);
     const float Pf = (float)P;
     const float u = (float)delta / Pf;
+    const float invP = 1.0f / Pf;
     const int kappa = TAPS > 0 ? (TAPS - 1) / 2 : d->kappa;
     const int taps = TAPS > 0 ? TAPS : d->taps;
     const int Q = d->Q;
     const float inv2sig2 = d->inv2sig2;
     const float wnorm = d->wnorm;
-    const float2* __restrict__ f = io.f;
-    float2* __restrict__ S = io.S + (size_t)Q * d->Moff[j] + l;
-    const float* __restrict__ rate = d->rate;
+    const GLOBAL float2* __restrict__ f = glb(io.f);
+    GLOBAL float2* __restrict__ S = glb(io.S) + (size_t)Q * d->Moff[j] + l;
+    const CONSTANT float* rate = cst(d->rate);
     const float step_rate = d->a_step;
     const bool interior = (jp - kappa >= 0) && (jp + kappa < N);
 
@@ -171,27 +223,25 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                 if (idx < 0) idx += N;
                 else if (idx >= N) idx -= N;
             }
-            x[i] = f[idx];
+            x[i] = ld2(f + idx);
         }
 #pragma unroll
         for (int i = 0; i < TAPS; ++i) {
-            const float w = tap_weight(delta, i - kappa, P, Pf, wnorm, inv2sig2);
+            const float w = tap_weight(delta, i - kappa, P, invP, wnorm, inv2sig2);
             x[i] = make_float2(x[i].x * w, x[i].y * w);
         }
         for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
             const int nb = min(kBandChunk, Q - b0);
             float2 acc[kBandChunk];
-            const float2* __restrict__ tab = d->bandtab + (size_t)b0 * TAPS;
+            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * TAPS;
 #pragma unroll
-            for (int bb = 0; bb < kBandChunk; ++bb) {
+            for (int bb = 0; bb < kBandChunk; ++bb) {   // the table is zero-padded to whole chunks
                 acc[bb] = make_float2(0.f, 0.f);
-                if (bb < nb) {
 #pragma unroll
-                    for (int i = 0; i < TAPS; ++i) {
-                        const float2 t = tab[bb * TAPS + i];
-                        acc[bb].x = fmaf(x[i].x, t.x, fmaf(-x[i].y, t.y, acc[bb].x));
-                        acc[bb].y = fmaf(x[i].x, t.y, fmaf(x[i].y, t.x, acc[bb].y));
-                    }
+                for (int i = 0; i < TAPS; ++i) {
+                    const float2 t = ld2(tab + bb * TAPS + i);
+                    acc[bb].x = fmaf(x[i].x, t.x, fmaf(-x[i].y, t.y, acc[bb].x));
+                    acc[bb].y = fmaf(x[i].x, t.y, fmaf(x[i].y, t.x, acc[bb].y));
                 }
             }
             store_bands(S, P, b0, nb, acc, u, rate, step_rate);
@@ -202,24 +252,22 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             float2 acc[kBandChunk];
 #pragma unroll
             for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = make_float2(0.f, 0.f);
-            const float2* __restrict__ tab = d->bandtab + (size_t)b0 * taps;
+            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * taps;
             for (int i = 0; i < taps; ++i) {
                 int64_t idx = jp - kappa + i;
                 if (!interior) {
                     if (idx < 0) idx += N;
                     else if (idx >= N) idx -= N;
                 }
-                const float w = tap_weight(delta, i - kappa, P, Pf, wnorm, inv2sig2);
-                const float2 fv = f[idx];
+                const float w = tap_weight(delta, i - kappa, P, invP, wnorm, inv2sig2);
+                const float2 fv = ld2(f + idx);
                 const float xr = fv.x * w;
                 const float xi = fv.y * w;
 #pragma unroll
-                for (int bb = 0; bb < kBandChunk; ++bb) {
-                    if (bb < nb) {
-                        const float2 t = tab[bb * taps + i];
-                        acc[bb].x = fmaf(xr, t.x, fmaf(-xi, t.y, acc[bb].x));
-                        acc[bb].y = fmaf(xr, t.y, fmaf(xi, t.x, acc[bb].y));
-                    }
+                for (int bb = 0; bb < kBandChunk; ++bb) {   // zero-padded table: no guard
+                    const float2 t = ld2(tab + bb * taps + i);
+                    acc[bb].x = fmaf(xr, t.x, fmaf(-xi, t.y, acc[bb].x));
+                    acc[bb].y = fmaf(xr, t.y, fmaf(xi, t.x, acc[bb].y));
                 }
             }
             store_bands(S, P, b0, nb, acc, u, rate, step_rate);
@@ -306,8 +354,8 @@ __device__ void fft_rows_lds(float2* buf, int rows, int s1, int lg, const float2
 // Cosine/sine table of a p-point step (host-computed per modulus), copied to
 // LDS: trig[(n - 1) h + (k - 1)] = (cos, sin)(2 pi (n k mod p) / p), n, k in [1, h].
 template <int NT>
-__device__ void load_trig(float2* trig, int h, const float2* __restrict__ src) {
-    for (int i = (int)threadIdx.x; i < h * h; i += NT) trig[i] = src[i];
+__device__ void load_trig(float2* trig, int h, const GLOBAL float2* __restrict__ src) {
+    for (int i = (int)threadIdx.x; i < h * h; i += NT) trig[i] = ld2(src + i);
 }
 
 constexpr int kDftKB = 8;       // output pairs per work item, split path
@@ -350,7 +398,7 @@ __device__ __forceinline__ void pfa_column_sums(const float2* blk, int stride, i
 // item per (column, group of kDftKB output pairs), written to out[k * out_stride + c].
 template <int NT>
 __device__ void dft_cols_lds(const float2* blk, int stride, int ncols, int p, const float2* trig,
-                             float2* __restrict__ out, int out_stride, float scale) {
+                             GLOBAL float2* __restrict__ out, int out_stride, float scale) {
     const int h = (p - 1) >> 1;
     const int ng = (h + kDftKB - 1) / kDftKB;
     const int groups = ng > 0 ? ng : 1;
@@ -365,13 +413,13 @@ __device__ void dft_cols_lds(const float2* blk, int stride, int ncols, int p, co
         for (int kk = 0; kk < kDftKB; ++kk) {
             const int k = k0 + kk;
             if (k <= h) {
-                out[(size_t)k * out_stride + c] =
-                    make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale);
-                out[(size_t)(p - k) * out_stride + c] =
-                    make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale);
+                st2(out + (size_t)k * out_stride + c,
+                    make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale));
+                st2(out + (size_t)(p - k) * out_stride + c,
+                    make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale));
             }
         }
-        if (g == 0) out[c] = make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale);
+        if (g == 0) st2(out + c, make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale));
     }
 }
 
@@ -488,7 +536,8 @@ __device__ int block_exclusive_sum(int v, int32_t* part) {
 // the same order (LDS broadcast).  CL must be writable by this workgroup only.
 template <int NT, class KeyF>
 __device__ void emit_heavy(KeyF key, int P, int T, int s1, int lg, int depth, uint64_t thr, uint64_t* hk,
-                           int32_t* __restrict__ H, uint64_t* __restrict__ thr_out, int32_t* __restrict__ CL) {
+                           GLOBAL int32_t* __restrict__ H, GLOBAL uint64_t* __restrict__ thr_out,
+                           GLOBAL int32_t* __restrict__ CL) {
     __shared__ int32_t sh_n;
     const int tid = (int)threadIdx.x;
     if (tid == 0) {
@@ -541,7 +590,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = kDftThreads;
     const Where at = locate(a);
-    const SigDesc* __restrict__ d = desc_of(a, at.sig);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
     const int tid = (int)threadIdx.x;
     const int Q = d->Q;
@@ -565,10 +614,10 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     int32_t* part = hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [2 T]
 
-    const float2* __restrict__ S = io.S + base;
-    for (int i = tid; i < P; i += NT) buf[i] = S[i];
-    for (int i = tid; i < (s1 >> 1); i += NT) tw[i] = d->tw_s1[i];
-    load_trig<NT>(trig, h, d->trig + d->trig_off[j]);
+    const GLOBAL float2* __restrict__ S = glb(io.S) + base;
+    for (int i = tid; i < P; i += NT) buf[i] = ld2(S + i);
+    for (int i = tid; i < (s1 >> 1); i += NT) tw[i] = ld2(glb(d->tw_s1) + i);
+    load_trig<NT>(trig, h, glb(d->trig) + d->trig_off[j]);
     __syncthreads();
     fft_rows_lds<NT>(buf, p, s1, lg, tw);
 
@@ -582,7 +631,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     float2 C[KBMAX], D[KBMAX], sa;
     pfa_column_sums<KBMAX>(buf, s1, c, p, h, k0, KB, trig, C, D, sa);
     __syncthreads();   // every column has been read: the block may be overwritten
-    float2* __restrict__ E = io.E + base;
+    GLOBAL float2* __restrict__ E = glb(io.E) + base;
     const float scale = 1.0f / (float)P;
     const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
     const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
@@ -594,27 +643,27 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
             const float2 xm = make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale);
             const int ik = (k << lg) + c;
             const int im = ((p - k) << lg) + c;
-            E[ik] = xk;
-            E[im] = xm;
+            st2(E + ik, xk);
+            st2(E + im, xm);
             keys[ik] = value_key(xk, pfa_bin(ik, lg, s1, (uint32_t)P, cA, cB));
             keys[im] = value_key(xm, pfa_bin(im, lg, s1, (uint32_t)P, cA, cB));
         }
     }
     if (g == 0) {
         const float2 xz = make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale);
-        E[c] = xz;
+        st2(E + c, xz);
         keys[c] = value_key(xz, pfa_bin(c, lg, s1, (uint32_t)P, cA, cB));
     }
     __syncthreads();
     auto kf = [&](int i) { return keys[i]; };
     const uint64_t thr = kth_largest<NT>(kf, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<NT>(kf, P, d->T, s1, lg, d->depth, thr, hk, io.H + blk * d->T, io.thr + blk,
-                   io.CL + blk * (size_t)s1 * d->depth);
+    emit_heavy<NT>(kf, P, d->T, s1, lg, d->depth, thr, hk, glb(io.H) + blk * d->T, glb(io.thr) + blk,
+                   glb(io.CL) + blk * (size_t)s1 * d->depth);
 }
 
 // Split path, step A: block -> (modulus j, band b, chunk of rows_per rows).
-__device__ __forceinline__ void split_rows_where(const SigDesc* d, int blk, int rows_per, int& j, int& b, int& chunk) {
+__device__ __forceinline__ void split_rows_where(const CONSTANT SigDesc* d, int blk, int rows_per, int& j, int& b, int& chunk) {
     const int Q = d->Q;
     j = 0;
     for (;;) {
@@ -632,7 +681,7 @@ __device__ __forceinline__ void split_rows_where(const SigDesc* d, int blk, int 
 __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
-    const SigDesc* __restrict__ d = desc_of(a, at.sig);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
     const int tid = (int)threadIdx.x;
     const int s1 = d->s1;
@@ -647,20 +696,20 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     float2* buf = reinterpret_cast<float2*>(smem);
     float2* tw = buf + ((size_t)rows_per << lg);
     const int n = rows << lg;
-    const float2* __restrict__ S = io.S + base;
-    for (int i = tid; i < n; i += kThreads) buf[i] = S[i];
-    for (int i = tid; i < (s1 >> 1); i += kThreads) tw[i] = d->tw_s1[i];
+    const GLOBAL float2* __restrict__ S = glb(io.S) + base;
+    for (int i = tid; i < n; i += kThreads) buf[i] = ld2(S + i);
+    for (int i = tid; i < (s1 >> 1); i += kThreads) tw[i] = ld2(glb(d->tw_s1) + i);
     __syncthreads();
     fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
-    float2* __restrict__ X = io.E + base;   // the bins' buffer holds the step-A result
-    for (int i = tid; i < n; i += kThreads) X[i] = buf[i];
+    GLOBAL float2* __restrict__ X = glb(io.E) + base;   // the bins' buffer holds the step-A result
+    for (int i = tid; i < n; i += kThreads) st2(X + i, buf[i]);
 }
 
 // Split path, step B: block -> (modulus j, band b, 64 columns); in place on E.
 __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
-    const SigDesc* __restrict__ d = desc_of(a, at.sig);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
     const int tid = (int)threadIdx.x;
     const int Q = d->Q;
@@ -680,13 +729,13 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
     float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]
     float2* trig = tile + (size_t)pmax * C;
-    float2* __restrict__ E = io.E + base;
+    GLOBAL float2* __restrict__ E = glb(io.E) + base;
     for (int i = tid; i < p * C; i += kThreads) {
         const int n2 = i / C;
         const int k1 = c0 + (i - n2 * C);
-        tile[i] = E[((size_t)n2 << lg) + k1];
+        tile[i] = ld2(E + ((size_t)n2 << lg) + k1);
     }
-    load_trig<kThreads>(trig, (p - 1) >> 1, d->trig + d->trig_off[j]);
+    load_trig<kThreads>(trig, (p - 1) >> 1, glb(d->trig) + d->trig_off[j]);
     __syncthreads();
     dft_cols_lds<kThreads>(tile, C, C, p, trig, E + c0, s1, 1.0f / (float)P);
 }
@@ -695,7 +744,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
 __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
-    const SigDesc* __restrict__ d = desc_of(a, at.sig);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
     const int Q = d->Q;
     const int j = at.blk / Q;
@@ -707,14 +756,14 @@ __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
     int32_t* hist = reinterpret_cast<int32_t*>(smem);
     int32_t* part = hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [2 T]
-    const float2* __restrict__ E = io.E + (size_t)Q * d->Moff[j] + (size_t)b * P;
+    const GLOBAL float2* __restrict__ E = glb(io.E) + (size_t)Q * d->Moff[j] + (size_t)b * P;
     const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
     const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
-    auto kf = [&](int i) { return value_key(E[i], pfa_bin(i, lg, s1, (uint32_t)P, cA, cB)); };
+    auto kf = [&](int i) { return value_key(ld2(E + i), pfa_bin(i, lg, s1, (uint32_t)P, cA, cB)); };
     const uint64_t thr = kth_largest<kThreads>(kf, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<kThreads>(kf, P, d->T, s1, lg, d->depth, thr, hk, io.H + blk * d->T, io.thr + blk,
-                         io.CL + blk * (size_t)s1 * d->depth);
+    emit_heavy<kThreads>(kf, P, d->T, s1, lg, d->depth, thr, hk, glb(io.H) + blk * d->T, glb(io.thr) + blk,
+                         glb(io.CL) + blk * (size_t)s1 * d->depth);
 }
 
 // ---------------------------------------------------------- k_identify ----
@@ -750,7 +799,7 @@ __device__ __forceinline__ float median_of(const float* v, int K) {
 __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
-    const SigDesc* __restrict__ d = desc_of(a, at.sig);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
     const int tid = (int)threadIdx.x;
     const int b = at.blk;
@@ -773,16 +822,16 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     uint8_t* ccount = reinterpret_cast<uint8_t*>(thr + kMaxK);                // [K * s1]
     __shared__ int32_t sh_cnt;
 
-    const int32_t* __restrict__ CLall = io.CL;
-    const float2* __restrict__ Eall = io.E;
+    const GLOBAL int32_t* __restrict__ CLall = glb(io.CL);
+    const GLOBAL float2* __restrict__ Eall = glb(io.E);
     const size_t cl_stride = (size_t)s1 * depth;   // one (modulus, band) block of class lists
 
     // 0. thresholds and class-list lengths of this band's K blocks, into LDS
-    for (int jj = tid; jj < K; jj += kThreads) thr[jj] = io.thr[jj * Q + b];
+    for (int jj = tid; jj < K; jj += kThreads) thr[jj] = glb(io.thr)[jj * Q + b];
     for (int i = tid; i < K * s1; i += kThreads) {
         const int jj = i >> lg;
         const int ac = i & (s1 - 1);
-        const int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
+        const GLOBAL int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
         int n = 0;
 #pragma unroll
         for (int e = 0; e < kMaxDepth; ++e) n += (e < depth && cl[e] >= 0) ? 1 : 0;   // lists are -1 padded
@@ -818,7 +867,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         int64_t x = (int64_t)((ac * (int64_t)d->tup_inv[t][0]) % s1) * d->tup_Mi[t][0];
         for (int g = 0; g < G; ++g) {
             const int jj = d->tup_j[t][g];
-            const int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
+            const GLOBAL int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
             const int cg = ccount[(jj << lg) + ac];
             const int ch = r % cg;
             r /= cg;
@@ -845,7 +894,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 const int hh = (int)pos_mod(w, Pj);
                 const int cls = hh & (s1 - 1);
                 const int k2 = hh % d->p[jj];
-                const float2 ev = Eall[(size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) + cls];
+                const float2 ev = ld2(Eall + (size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) + cls);
                 const bool heavy = value_key(ev, (uint32_t)hh) >= thr[jj];
                 votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
                 er[jj] = ev.x;
@@ -901,8 +950,8 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     block_exclusive_scan(flag, nacc, scratch);   // for a distinct entry: its rank among distinct ones
     const int64_t q = d->q_first + 2 * (int64_t)b * d->L;
     const int s = d->s;
-    int64_t* __restrict__ Rw = io.Rw + (size_t)b * s;
-    double2* __restrict__ Rv = io.Rv + (size_t)b * s;
+    GLOBAL int64_t* __restrict__ Rw = glb(io.Rw) + (size_t)b * s;
+    GLOBAL double2* __restrict__ Rv = glb(io.Rv) + (size_t)b * s;
     // in-band results are written in sorted order by a serial pass of wave 0
     if (tid < 64) {
         int outc = 0;
@@ -925,11 +974,11 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 const double gh = d->ghat0 * exp(-d->c1sq_half * n * n);
                 const float2 z = az[i];
                 Rw[o] = w;
-                Rv[o] = make_double2((double)z.x / gh, (double)z.y / gh);
+                std2(Rv + o, make_double2((double)z.x / gh, (double)z.y / gh));
             }
             outc += __popcll(ballot);
         }
-        if (tid == 0) io.Rn[b] = outc;
+        if (tid == 0) glb(io.Rn)[b] = outc;
     }
 }
 
@@ -944,7 +993,7 @@ __device__ __forceinline__ bool merge_before(double ma, int64_t wa, double mb, i
 __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
-    const SigDesc* __restrict__ d = desc_of(a, at.sig);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
     const IoDesc io = io_of(a, at.sig);
     const int tid = (int)threadIdx.x;
     const int Q = d->Q;
@@ -955,20 +1004,20 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
     int32_t* off = src + kMergeCap;
     int32_t* scratch = off + SFT_MAX_BANDS + 1;
 
-    for (int bb = tid; bb < Q; bb += kThreads) off[bb] = io.Rn[bb];
+    for (int bb = tid; bb < Q; bb += kThreads) off[bb] = glb(io.Rn)[bb];
     __syncthreads();
     const int total = block_exclusive_scan(off, Q, scratch);
     const int n = min(total, kMergeCap);
     if (tid == 0 && total > kMergeCap) atomicOr(io.status, kStatusMergeOverflow);
     for (int bb = 0; bb < Q; ++bb) {
-        const int cnt = io.Rn[bb];
+        const int cnt = glb(io.Rn)[bb];
         const int o = off[bb];
         for (int k = tid; k < cnt; k += kThreads) {
             const int dst = o + k;
             if (dst < n) {
-                const double2 v = io.Rv[(size_t)bb * s + k];
+                const double2 v = ldd2(glb(io.Rv) + (size_t)bb * s + k);
                 mm[dst] = v.x * v.x + v.y * v.y;
-                ww[dst] = io.Rw[(size_t)bb * s + k];
+                ww[dst] = glb(io.Rw)[(size_t)bb * s + k];
                 src[dst] = bb * s + k;
             }
         }
@@ -1007,15 +1056,15 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
     const int nout = min(n, s);
     for (int r = tid; r < s; r += kThreads) {
         if (r < nout) {
-            const double2 v = io.Rv[src[r]];
-            io.out_w[r] = ww[r];
-            io.out_c[r] = make_float2((float)v.x, (float)v.y);
+            const double2 v = ldd2(glb(io.Rv) + src[r]);
+            glb(io.out_w)[r] = ww[r];
+            st2(glb(io.out_c) + r, make_float2((float)v.x, (float)v.y));
         } else {
-            io.out_w[r] = 0;
-            io.out_c[r] = make_float2(0.f, 0.f);
+            glb(io.out_w)[r] = 0;
+            st2(glb(io.out_c) + r, make_float2(0.f, 0.f));
         }
     }
-    if (tid == 0 && io.out_n) io.out_n[0] = nout;
+    if (tid == 0 && io.out_n) glb(io.out_n)[0] = nout;
 }
 
 // ------------------------------------------------------------ launchers ---

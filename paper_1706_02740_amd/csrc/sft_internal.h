@@ -78,14 +78,17 @@ struct IoDesc {
     int32_t* status;  // [1]
 };
 
-// Kernel launch argument: one transform (descs_many == nullptr) or a batch.
+// Kernel launch argument: one transform (io_many == nullptr), a batch of one
+// plan (bps > 0: transform i owns blocks [i bps, (i + 1) bps) and desc_one is
+// its descriptor), or a batch of several plans (prefix table + descriptors).
 struct BatchArgs {
     const SigDesc* desc_one;
     IoDesc io_one;
-    const SigDesc* const* descs_many;  // [nsig] device array of plan descriptors
+    const SigDesc* const* descs_many;  // [nsig] device array of plan descriptors (mixed batches)
     const IoDesc* io_many;             // [nsig]
-    const int32_t* prefix;             // [nsig+1] first block of each signal for this kernel
+    const int32_t* prefix;             // [nsig+1] first block of each signal for this kernel (mixed)
     int32_t nsig;
+    int32_t bps;                       // blocks per transform of a one-plan batch, else 0
 };
 
 // Per-signal workspace sizes in bytes (each slice 256-byte aligned).
