@@ -554,6 +554,21 @@ int sft_plan_fetch(const sft_plan_t plan, int32_t what, void* dst, size_t bytes,
     HIP_TRY(hipStreamSynchronize(plan->last_stream), "hipStreamSynchronize");
     if (what != SFT_FETCH_BANDS) {
         HIP_TRY(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost), "hipMemcpy(fetch)");
+        if (what == SFT_FETCH_HEAVY) {
+            // the device writes each block's heavy bins in any order: sort them
+            // by Good-Thomas position (h mod s1) + s1 (h mod p_j)
+            int32_t* H = static_cast<int32_t*>(dst);
+            const int64_t s1 = in.s1;
+            for (int j = 0; j < in.K; ++j) {
+                const int64_t pj = in.primes[j];
+                for (int b = 0; b < in.Q; ++b) {
+                    int32_t* blk = H + ((size_t)j * in.Q + b) * in.T;
+                    std::sort(blk, blk + in.T, [&](int32_t x, int32_t y) {
+                        return x % s1 + s1 * (x % pj) < y % s1 + s1 * (y % pj);
+                    });
+                }
+            }
+        }
         return SFT_OK;
     }
     // counts[Q], then Q*s records {int64 w; double re; double im}, band b's at b*s

@@ -52,6 +52,31 @@ __device__ __forceinline__ void st2(GLOBAL float2* p, float2 v) {
     w.y = v.y;
     *(GLOBAL pod_f2*)p = w;
 }
+typedef float pod_f4 __attribute__((ext_vector_type(4)));
+
+// Copies n float2 (n even, both ends 16-byte aligned) from global memory into
+// LDS, 16 bytes per access, with U accesses of a thread in flight before its
+// first LDS write (a plain loop would wait for each load in turn).
+template <int NT, int U>
+__device__ __forceinline__ void copy_to_lds(float2* dst, const GLOBAL float2* src, int n) {
+    const int n4 = n >> 1;
+    const GLOBAL pod_f4* s4 = (const GLOBAL pod_f4*)src;
+    pod_f4* d4 = (pod_f4*)dst;
+    for (int i0 = (int)threadIdx.x; i0 < n4; i0 += U * NT) {
+        pod_f4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * NT;
+            if (i < n4) v[u] = s4[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * NT;
+            if (i < n4) d4[i] = v[u];
+        }
+    }
+}
+
 __device__ __forceinline__ double2 ldd2(const GLOBAL double2* p) {
     const pod_d2 v = *(const GLOBAL pod_d2*)p;
     return make_double2(v.x, v.y);
@@ -445,8 +470,9 @@ __device__ __forceinline__ uint32_t pfa_bin(int i, int lg, int s1, uint32_t P, u
 constexpr int kSelBits = 10;
 static_assert(kSelBins == 1 << kSelBits, "bucket count");
 
-template <int NT, class KeyF>
-__device__ uint64_t kth_largest(KeyF key, int P, int T, int32_t* hist, int32_t* part) {
+// each(f) calls f(k) for every key k this thread holds.
+template <int NT, class EachKey>
+__device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32_t* part) {
     __shared__ int32_t sh_digit, sh_need, sh_done;
     constexpr int BPT = kSelBins / NT;   // buckets per thread
     const int tid = (int)threadIdx.x;
@@ -462,10 +488,9 @@ __device__ uint64_t kth_largest(KeyF key, int P, int T, int32_t* hist, int32_t* 
         const uint64_t dmask = ((uint64_t)1 << width) - 1;
         for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
         __syncthreads();
-        for (int i = tid; i < P; i += NT) {
-            const uint64_t k = key(i);
+        each([&](uint64_t k) {
             if ((k & pmask) == prefix) atomicAdd(&hist[(int)((k >> shift) & dmask)], 1);
-        }
+        });
         __syncthreads();
         const int nb = 1 << width;
         int cnt[BPT];
@@ -527,64 +552,162 @@ __device__ int block_exclusive_sum(int v, int32_t* part) {
     return base + x - v;
 }
 
-// Heavy bins of one block (keys >= thr).  Writes the threshold, the heavy bins
-// in ascending Good-Thomas position (H[T]), and for every residue class c mod
-// s1 (column c of the [p][s1] layout) the `depth` heaviest heavy bins of the
-// class in descending key order (CL[c * depth + e], -1 where fewer).  The T
-// heavy keys are gathered once into hk (LDS, T entries); each one's position
-// rank and class rank then come from a scan of hk that every lane reads in
-// the same order (LDS broadcast).  CL must be writable by this workgroup only.
+// Heavy bins of one block (keys >= thr, at most T of them).  Writes the
+// threshold, the heavy bins in ascending Good-Thomas position (H), and for
+// every residue class c mod s1 (column c of the [p][s1] layout) the `depth`
+// heaviest heavy bins of the class in descending key order (CL[c * depth + e],
+// -1 where fewer).  Wave w walks the contiguous positions [w seg, (w + 1) seg)
+// 64 at a time; a ballot per step gives each heavy bin its rank within the
+// wave, a scan of the per-wave counts its rank in the block, so H comes out in
+// position order without sorting.  Class ranks come from pairwise key
+// comparisons of the heavy (key, position) pairs (hk), split over all threads.
+// scr: LDS int32[kSelBins]; part: LDS int32[NT / 64]; hk: LDS uint64[2 T];
+// cl: LDS int32[s1 * depth].
 template <int NT, class KeyF>
-__device__ void emit_heavy(KeyF key, int P, int T, int s1, int lg, int depth, uint64_t thr, uint64_t* hk,
-                           GLOBAL int32_t* __restrict__ H, GLOBAL uint64_t* __restrict__ thr_out,
-                           GLOBAL int32_t* __restrict__ CL) {
+__device__ void emit_heavy(KeyF key, int P, int T, int s1, int depth, uint64_t thr, uint64_t* hk, int32_t* scr,
+                           int32_t* part, int32_t* cl, GLOBAL int32_t* __restrict__ H,
+                           GLOBAL uint64_t* __restrict__ thr_out, GLOBAL int32_t* __restrict__ CL) {
+    constexpr int W = NT / 64;
     __shared__ int32_t sh_n;
     const int tid = (int)threadIdx.x;
-    if (tid == 0) {
-        *thr_out = thr;
-        sh_n = 0;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const uint64_t lt = ((uint64_t)1 << lane) - 1;
+    const int seg = ((P + NT - 1) / NT) * 64;   // positions per wave, a multiple of 64
+    const int p0 = wid * seg;
+    const int p1 = min(P, p0 + seg);
+    if (tid == 0) *thr_out = thr;
+    for (int i = tid; i < s1 * depth; i += NT) cl[i] = -1;
+
+    int cnt = 0;   // heavy bins in this wave's segment (wave-uniform)
+    for (int i0 = p0; i0 < p1; i0 += 64) {
+        const int i = i0 + lane;
+        cnt += __popcll(__ballot(i < p1 && key(i) >= thr));
     }
-    for (int i = tid; i < s1 * depth; i += NT) CL[i] = -1;
+    if (lane == 0) part[wid] = cnt;
     __syncthreads();
-    // keys carry h in their low half; the position is recovered from the bin
-    // below, so hk holds (key, position) pairs packed as key with the position
-    // in a parallel slot: hk[2e] = key, hk[2e + 1] = position.
-    for (int i = tid; i < P; i += NT) {
-        const uint64_t k = key(i);
-        if (k >= thr) {
-            const int e = atomicAdd(&sh_n, 1);
+    int run = 0;
+    for (int w = 0; w < wid; ++w) run += part[w];
+    if (tid == NT - 1) sh_n = run + cnt;
+    for (int i0 = p0; i0 < p1; i0 += 64) {
+        const int i = i0 + lane;
+        uint64_t k = 0;
+        const bool hv = i < p1 && (k = key(i)) >= thr;
+        const uint64_t m = __ballot(hv);
+        if (hv) {
+            const int e = run + __popcll(m & lt);
             if (e < T) {
                 hk[2 * e] = k;
                 hk[2 * e + 1] = (uint64_t)i;
+                H[e] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
             }
         }
+        run += __popcll(m);
     }
     __syncthreads();
     const int n = min(sh_n, T);
-    for (int e = tid; e < n; e += NT) {
-        const uint64_t k = hk[2 * e];
-        const int pos = (int)hk[2 * e + 1];
-        const uint32_t h = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
-        const int cls = pos & (s1 - 1);   // = h mod s1
-        int before = 0, heavier = 0;
-        for (int f = 0; f < n; ++f) {
-            const uint64_t kf = hk[2 * f];
-            const int pf = (int)hk[2 * f + 1];
-            before += pf < pos ? 1 : 0;
-            heavier += ((pf & (s1 - 1)) == cls && kf > k) ? 1 : 0;
+
+    // class ranks: heavier[e] = number of heavy bins of e's class with a larger key
+    const int parts = n > 0 ? min(64, NT / n) : 1;
+    int32_t* heavier = scr;
+    if (parts > 1) {   // n <= NT / 2 <= kSelBins
+        for (int e = tid; e < n; e += NT) heavier[e] = 0;
+        __syncthreads();
+        const int span = (n + parts - 1) / parts;
+        for (int it = tid; it < n * parts; it += NT) {
+            const int q = it / n;          // lanes of a wave share q: the hk reads are broadcasts
+            const int e = it - q * n;
+            const uint64_t k = hk[2 * e];
+            const int cls = (int)hk[2 * e + 1] & (s1 - 1);
+            const int f1 = min(n, (q + 1) * span);
+            int c = 0;
+            for (int f = q * span; f < f1; ++f) c += (((int)hk[2 * f + 1] & (s1 - 1)) == cls && hk[2 * f] > k) ? 1 : 0;
+            if (c) atomicAdd(&heavier[e], c);
         }
-        H[before] = (int32_t)h;
-        if (heavier < depth) CL[cls * depth + heavier] = (int32_t)h;
+        __syncthreads();
+        for (int e = tid; e < n; e += NT) {
+            const int r = heavier[e];
+            if (r < depth) {
+                const uint64_t k = hk[2 * e];
+                cl[((int)hk[2 * e + 1] & (s1 - 1)) * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+            }
+        }
+    } else {
+        for (int e = tid; e < n; e += NT) {
+            const uint64_t k = hk[2 * e];
+            const int cls = (int)hk[2 * e + 1] & (s1 - 1);
+            int r = 0;
+            for (int f = 0; f < n; ++f) r += (((int)hk[2 * f + 1] & (s1 - 1)) == cls && hk[2 * f] > k) ? 1 : 0;
+            if (r < depth) cl[cls * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+        }
     }
-    (void)lg;
+    __syncthreads();
+    for (int i = tid; i < s1 * depth; i += NT) CL[i] = cl[i];
 }
+
+// emit_heavy for keys held in registers: thread tid holds up to NK keys of
+// residue class c (slot q valid when bit q of `valid` is set); the threads of
+// class c are (g << lg) + c, g < NT >> lg.  Same outputs, except that H holds
+// the heavy bins in an unspecified order.  Each thread's heavy keys go to hk
+// at its exclusive-sum offset; a heavy key's class rank counts the heavier
+// keys in the hk ranges of the threads of its class.
+// offs: LDS int32[2 NT]; part: LDS int32[NT / 64]; hk: LDS uint64[T];
+// cl: LDS int32[s1 * depth].
+template <int NT, int NK>
+__device__ void emit_heavy_regs(const uint64_t (&key)[NK], uint64_t valid, int c, int lg, int T, int depth,
+                                uint64_t thr, uint64_t* hk, int32_t* offs, int32_t* part, int32_t* cl,
+                                GLOBAL int32_t* __restrict__ H, GLOBAL uint64_t* __restrict__ thr_out,
+                                GLOBAL int32_t* __restrict__ CL) {
+    const int tid = (int)threadIdx.x;
+    const int s1 = 1 << lg;
+    if (tid == 0) *thr_out = thr;
+    for (int i = tid; i < s1 * depth; i += NT) cl[i] = -1;
+    static_assert(NK <= 64, "slot mask");
+    uint64_t hm = 0;
+#pragma unroll
+    for (int q = 0; q < NK; ++q)
+        if (((valid >> q) & 1) && key[q] >= thr) hm |= (uint64_t)1 << q;
+    const int cnt = __popcll(hm);
+    const int ex = block_exclusive_sum<NT>(cnt, part);
+    offs[tid] = ex;
+    offs[NT + tid] = cnt;
+    int e = ex;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        if ((hm >> q) & 1) {
+            if (e < T) {
+                hk[e] = key[q];
+                H[e] = (int32_t)(0xffffffffu - (uint32_t)(key[q] & 0xffffffffu));
+            }
+            ++e;
+        }
+    }
+    __syncthreads();
+    const int ng = NT >> lg;
+    for (int e1 = ex; e1 < min(ex + cnt, T); ++e1) {
+        const uint64_t k = hk[e1];
+        int r = 0;
+        for (int g2 = 0; g2 < ng; ++g2) {
+            const int t2 = (g2 << lg) + c;
+            const int o2 = offs[t2];
+            const int o3 = min(o2 + offs[NT + t2], T);
+            for (int e2 = o2; e2 < o3; ++e2) r += hk[e2] > k ? 1 : 0;
+        }
+        if (r < depth) cl[c * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+    }
+    __syncthreads();
+    for (int i = tid; i < s1 * depth; i += NT) CL[i] = cl[i];
+}
+
+static_assert(2 * kDftThreads <= kSelBins, "emit_heavy_regs offsets live in the histogram");
 
 // One workgroup per (modulus j, band b); the whole block in LDS.  Requires
 // s1 <= kDftThreads and ceil(h / (kDftThreads / s1)) <= KBMAX, h = (p-1)/2
 // (KBMAX = 8 keeps two workgroups per CU; 16 serves s1 = 256).
 // Step B runs one work item per thread (output group g = tid / s1 of column
-// c = tid mod s1); the results stay in registers across a barrier and are then
-// written to E, while their selection keys overwrite the LDS block.
+// c = tid mod s1); the results are written to E and their selection keys stay
+// in registers for the selection (slots 2 kk and 2 kk + 1: rows k0 + kk and
+// p - k0 - kk; slot 2 KBMAX: row 0, group 0 only).
 template <int KBMAX>
 __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -607,15 +730,15 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
 
     float2* buf = reinterpret_cast<float2*>(smem);
-    uint64_t* keys = reinterpret_cast<uint64_t*>(smem);
     float2* tw = reinterpret_cast<float2*>(smem + (size_t)Pmax * 8);
     float2* trig = tw + (s1 >> 1);
     int32_t* hist = reinterpret_cast<int32_t*>(trig + hmax * hmax);
     int32_t* part = hist + kSelBins;
-    uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [2 T]
+    uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [T]
+    int32_t* cl = reinterpret_cast<int32_t*>(hk + d->T);        // [s1 depth]
 
     const GLOBAL float2* __restrict__ S = glb(io.S) + base;
-    for (int i = tid; i < P; i += NT) buf[i] = ld2(S + i);
+    copy_to_lds<NT, 8>(buf, S, P);
     for (int i = tid; i < (s1 >> 1); i += NT) tw[i] = ld2(glb(d->tw_s1) + i);
     load_trig<NT>(trig, h, glb(d->trig) + d->trig_off[j]);
     __syncthreads();
@@ -630,14 +753,17 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const float2 x0 = buf[c];
     float2 C[KBMAX], D[KBMAX], sa;
     pfa_column_sums<KBMAX>(buf, s1, c, p, h, k0, KB, trig, C, D, sa);
-    __syncthreads();   // every column has been read: the block may be overwritten
     GLOBAL float2* __restrict__ E = glb(io.E) + base;
     const float scale = 1.0f / (float)P;
     const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
     const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
+    constexpr int NK = 2 * KBMAX + 1;
+    uint64_t key[NK];
+    uint64_t valid = 0;
 #pragma unroll
     for (int kk = 0; kk < KBMAX; ++kk) {
         const int k = k0 + kk;
+        key[2 * kk] = key[2 * kk + 1] = 0;
         if (kk < KB && k <= h) {
             const float2 xk = make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale);
             const float2 xm = make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale);
@@ -645,21 +771,27 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
             const int im = ((p - k) << lg) + c;
             st2(E + ik, xk);
             st2(E + im, xm);
-            keys[ik] = value_key(xk, pfa_bin(ik, lg, s1, (uint32_t)P, cA, cB));
-            keys[im] = value_key(xm, pfa_bin(im, lg, s1, (uint32_t)P, cA, cB));
+            key[2 * kk] = value_key(xk, pfa_bin(ik, lg, s1, (uint32_t)P, cA, cB));
+            key[2 * kk + 1] = value_key(xm, pfa_bin(im, lg, s1, (uint32_t)P, cA, cB));
+            valid |= (uint64_t)3 << (2 * kk);
         }
     }
+    key[NK - 1] = 0;
     if (g == 0) {
         const float2 xz = make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale);
         st2(E + c, xz);
-        keys[c] = value_key(xz, pfa_bin(c, lg, s1, (uint32_t)P, cA, cB));
+        key[NK - 1] = value_key(xz, pfa_bin(c, lg, s1, (uint32_t)P, cA, cB));
+        valid |= (uint64_t)1 << (NK - 1);
     }
-    __syncthreads();
-    auto kf = [&](int i) { return keys[i]; };
-    const uint64_t thr = kth_largest<NT>(kf, P, d->T, hist, part);
+    auto each = [&](auto f) {
+#pragma unroll
+        for (int q = 0; q < NK; ++q)
+            if ((valid >> q) & 1) f(key[q]);
+    };
+    const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<NT>(kf, P, d->T, s1, lg, d->depth, thr, hk, glb(io.H) + blk * d->T, glb(io.thr) + blk,
-                   glb(io.CL) + blk * (size_t)s1 * d->depth);
+    emit_heavy_regs<NT, NK>(key, valid, c, lg, d->T, d->depth, thr, hk, hist, part, cl, glb(io.H) + blk * d->T,
+                            glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
 }
 
 // Split path, step A: block -> (modulus j, band b, chunk of rows_per rows).
@@ -697,7 +829,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     float2* tw = buf + ((size_t)rows_per << lg);
     const int n = rows << lg;
     const GLOBAL float2* __restrict__ S = glb(io.S) + base;
-    for (int i = tid; i < n; i += kThreads) buf[i] = ld2(S + i);
+    copy_to_lds<kThreads, 8>(buf, S, n);
     for (int i = tid; i < (s1 >> 1); i += kThreads) tw[i] = ld2(glb(d->tw_s1) + i);
     __syncthreads();
     fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
@@ -730,10 +862,22 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]
     float2* trig = tile + (size_t)pmax * C;
     GLOBAL float2* __restrict__ E = glb(io.E) + base;
-    for (int i = tid; i < p * C; i += kThreads) {
-        const int n2 = i / C;
-        const int k1 = c0 + (i - n2 * C);
-        tile[i] = ld2(E + ((size_t)n2 << lg) + k1);
+    constexpr int U = 8;   // loads of a thread in flight before its LDS writes
+    for (int i0 = tid; i0 < p * C; i0 += U * kThreads) {
+        float2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kThreads;
+            if (i < p * C) {
+                const int n2 = i / C;
+                v[u] = ld2(E + ((size_t)n2 << lg) + c0 + (i - n2 * C));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kThreads;
+            if (i < p * C) tile[i] = v[u];
+        }
     }
     load_trig<kThreads>(trig, (p - 1) >> 1, glb(d->trig) + d->trig_off[j]);
     __syncthreads();
@@ -756,14 +900,18 @@ __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
     int32_t* hist = reinterpret_cast<int32_t*>(smem);
     int32_t* part = hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [2 T]
+    int32_t* cl = reinterpret_cast<int32_t*>(hk + 2 * d->T);   // [s1 depth]
     const GLOBAL float2* __restrict__ E = glb(io.E) + (size_t)Q * d->Moff[j] + (size_t)b * P;
     const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
     const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
     auto kf = [&](int i) { return value_key(ld2(E + i), pfa_bin(i, lg, s1, (uint32_t)P, cA, cB)); };
-    const uint64_t thr = kth_largest<kThreads>(kf, P, d->T, hist, part);
+    auto each = [&](auto f) {
+        for (int i = (int)threadIdx.x; i < P; i += kThreads) f(kf(i));
+    };
+    const uint64_t thr = kth_largest<kThreads>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<kThreads>(kf, P, d->T, s1, lg, d->depth, thr, hk, glb(io.H) + blk * d->T, glb(io.thr) + blk,
-                         glb(io.CL) + blk * (size_t)s1 * d->depth);
+    emit_heavy<kThreads>(kf, P, d->T, s1, d->depth, thr, hk, hist, part, cl, glb(io.H) + blk * d->T,
+                         glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
 }
 
 // ---------------------------------------------------------- k_identify ----
@@ -1103,7 +1251,9 @@ size_t cols_lds_bytes(const SigDesc& d) {
     const size_t h = (size_t)(pmax - 1) / 2;
     return (size_t)pmax * std::min(kColChunk, d.s1) * 8 + h * h * 8 + 64;
 }
-size_t select_lds_bytes(const SigDesc& d) { return kSelBins * 4 + 64 + (size_t)d.T * 16 + 64; }
+size_t select_lds_bytes(const SigDesc& d) {
+    return kSelBins * 4 + 64 + (size_t)d.T * 16 + (size_t)d.s1 * d.depth * 4 + 64;
+}
 
 // Dynamic LDS above 64 KiB: raise each kernel's limit where the runtime asks
 // for an opt-in.  A rejected request is not an error here: the launch itself
