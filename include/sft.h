@@ -71,8 +71,11 @@ extern "C" {
  * (default 1: s1 = least power of two >= 2 s); group is G, the number of
  * primes per CRT tuple (default max(2, ceil(log2(N/s1)/6))); heavy_T is the
  * number of heavy bins kept per short DFT (default 2 s).  dft_path chooses the
- * short-DFT kernels: 0 = automatic (a whole block in LDS when it fits, else
- * the split path), 1 = in LDS, 2 = split; both give bitwise equal results.
+ * short-DFT kernels: 0 = automatic (a whole block in LDS with the p-point
+ * step on the matrix cores when s1 is 64 or 128 and every (p_j - 1)/2 < 32,
+ * else in LDS on the vector ALUs when it fits, else the split path),
+ * 1 = in LDS on the vector ALUs, 2 = split, 3 = in LDS on the matrix cores.
+ * Paths 1 and 2 give bitwise equal results; path 3 sums in another order.
  */
 typedef struct sft_params {
     int32_t preset;
@@ -214,7 +217,8 @@ SFT_API const char* sft_last_error(void);
 #define SFT_KERNEL_DFT_ROWS 4   /* split path for blocks larger than LDS: radix-2 row FFTs */
 #define SFT_KERNEL_DFT_COLS 5   /* split path: p-point column DFTs */
 #define SFT_KERNEL_SELECT   6   /* split path: heavy-bin selection from global memory */
-#define SFT_KERNEL_COUNT    7
+#define SFT_KERNEL_DFT_MX   7   /* as SFT_KERNEL_DFT, the p-point step on the matrix cores */
+#define SFT_KERNEL_COUNT    8
 SFT_API int sft_profile_enable(int32_t on);
 SFT_API int sft_profile_reset(void);
 SFT_API int sft_profile_read(int32_t kernel, int64_t* launches, double* total_ms);

@@ -41,7 +41,7 @@ struct sft_plan_s {
     WorkspaceLayout wl;
     IoDesc ws_io;           // workspace slices (f and outputs unset)
     size_t footprint = 0;
-    size_t lds[SFT_KERNEL_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    size_t lds[SFT_KERNEL_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
     int blocks[SFT_KERNEL_COUNT] = {0, 0, 0, 0, 0, 0, 0};   // per transform; 0 = kernel not used
     bool split = false;     // short DFTs too large for one workgroup's LDS
     int device = 0;
@@ -127,16 +127,22 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     SigDesc& d = pl->hdesc;
     const size_t lds_cap = (size_t)lds_limit - 256;   // room for the kernels' static LDS
     const int path = p ? p->dft_path : 0;
-    if (path < 0 || path > 2) {
+    if (path < 0 || path > 3) {
         delete pl;
-        return fail(SFT_EINVAL, "dft_path must be 0, 1 or 2");
+        return fail(SFT_EINVAL, "dft_path must be 0, 1, 2 or 3");
     }
     const bool fits = dft_fits_one_workgroup(d) && dft_lds_bytes(d) <= lds_cap;
+    const int mx = dft_mfma_variant(d);
+    const bool mx_fits = mx != 0 && dft_lds_bytes(d) <= lds_cap;
     if (path == 1 && !fits) {
         delete pl;
         return fail(SFT_EUNSUPPORTED, "the in-LDS short-DFT kernel cannot hold this plan (use dft_path 0 or 2)");
     }
-    pl->split = path == 2 || (path == 0 && !fits);
+    if (path == 3 && !mx_fits) {
+        delete pl;
+        return fail(SFT_EUNSUPPORTED, "the matrix-core short-DFT kernel does not cover this plan (use dft_path 0)");
+    }
+    pl->split = path == 2 || (path == 0 && !fits && !mx_fits);
     pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
     pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d);
     pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
@@ -144,9 +150,15 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);
     pl->blocks[SFT_KERNEL_MERGE] = merge_blocks(d);
     if (!pl->split) {
-        // low 32 bits: LDS bytes; above: output pairs per thread (selects the kernel variant)
-        pl->lds[SFT_KERNEL_DFT] = dft_lds_bytes(d) | ((size_t)dft_pairs_per_thread(d) << 32);
-        pl->blocks[SFT_KERNEL_DFT] = dft_blocks(d);
+        const bool use_mx = path == 3 || (path == 0 && mx_fits);
+        if (use_mx) {
+            pl->lds[SFT_KERNEL_DFT_MX] = dft_lds_bytes(d);
+            pl->blocks[SFT_KERNEL_DFT_MX] = dft_blocks(d);
+        } else {
+            // low 32 bits: LDS bytes; above: output pairs per thread (selects the kernel variant)
+            pl->lds[SFT_KERNEL_DFT] = dft_lds_bytes(d) | ((size_t)dft_pairs_per_thread(d) << 32);
+            pl->blocks[SFT_KERNEL_DFT] = dft_blocks(d);
+        }
     } else {
         pl->lds[SFT_KERNEL_DFT_ROWS] = rows_lds_bytes(d);
         pl->lds[SFT_KERNEL_DFT_COLS] = cols_lds_bytes(d);
@@ -321,10 +333,12 @@ hipError_t launch_gather_l(const BatchArgs& a, int b, size_t taps, hipStream_t s
 hipError_t launch_merge_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_merge(a, b, st); }
 
 // Launch order of the pipeline and the launcher of each kernel id.
-const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER, SFT_KERNEL_DFT, SFT_KERNEL_DFT_ROWS, SFT_KERNEL_DFT_COLS,
-                                      SFT_KERNEL_SELECT, SFT_KERNEL_IDENTIFY, SFT_KERNEL_MERGE};
-const char* kNames[SFT_KERNEL_COUNT] = {"launch(gather)", "launch(dft)", "launch(identify)", "launch(merge)",
-                                        "launch(dft_rows)", "launch(dft_cols)", "launch(select)"};
+const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER,    SFT_KERNEL_DFT_MX, SFT_KERNEL_DFT,
+                                      SFT_KERNEL_DFT_ROWS,  SFT_KERNEL_DFT_COLS, SFT_KERNEL_SELECT,
+                                      SFT_KERNEL_IDENTIFY,  SFT_KERNEL_MERGE};
+const char* kNames[SFT_KERNEL_COUNT] = {"launch(gather)",   "launch(dft)",      "launch(identify)",
+                                        "launch(merge)",    "launch(dft_rows)", "launch(dft_cols)",
+                                        "launch(select)",   "launch(dft_mx)"};
 
 LaunchFn launcher(int k) {
     switch (k) {
@@ -334,6 +348,7 @@ LaunchFn launcher(int k) {
         case SFT_KERNEL_MERGE: return launch_merge_l;
         case SFT_KERNEL_DFT_ROWS: return launch_dft_rows;
         case SFT_KERNEL_DFT_COLS: return launch_dft_cols;
+        case SFT_KERNEL_DFT_MX: return launch_dft_mx;
         default: return launch_select;
     }
 }

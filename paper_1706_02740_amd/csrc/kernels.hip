@@ -470,7 +470,9 @@ __device__ __forceinline__ uint32_t pfa_bin(int i, int lg, int s1, uint32_t P, u
 constexpr int kSelBits = 10;
 static_assert(kSelBins == 1 << kSelBits, "bucket count");
 
-// each(f) calls f(k) for every key k this thread holds.
+// each(f) calls f(hi, full) for every key k this thread holds, with hi = k >> 32
+// and full() returning k (which may cost more: it is called only in passes
+// whose digit reaches below bit 32, and only for keys whose hi matches).
 template <int NT, class EachKey>
 __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32_t* part) {
     __shared__ int32_t sh_digit, sh_need, sh_done;
@@ -488,9 +490,21 @@ __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32
         const uint64_t dmask = ((uint64_t)1 << width) - 1;
         for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
         __syncthreads();
-        each([&](uint64_t k) {
-            if ((k & pmask) == prefix) atomicAdd(&hist[(int)((k >> shift) & dmask)], 1);
-        });
+        const uint32_t pm_hi = (uint32_t)(pmask >> 32), pre_hi = (uint32_t)(prefix >> 32);
+        if (shift >= 32) {
+            const int sh = shift - 32;
+            const uint32_t dm = (uint32_t)dmask;
+            each([&](uint32_t hi, auto) {
+                if ((hi & pm_hi) == pre_hi) atomicAdd(&hist[(int)((hi >> sh) & dm)], 1);
+            });
+        } else {
+            each([&](uint32_t hi, auto full) {
+                if ((hi & pm_hi) == pre_hi) {
+                    const uint64_t k = full();
+                    if ((k & pmask) == prefix) atomicAdd(&hist[(int)((k >> shift) & dmask)], 1);
+                }
+            });
+        }
         __syncthreads();
         const int nb = 1 << width;
         int cnt[BPT];
@@ -645,16 +659,19 @@ __device__ void emit_heavy(KeyF key, int P, int T, int s1, int depth, uint64_t t
     for (int i = tid; i < s1 * depth; i += NT) CL[i] = cl[i];
 }
 
-// emit_heavy for keys held in registers: thread tid holds up to NK keys of
-// residue class c (slot q valid when bit q of `valid` is set); the threads of
-// class c are (g << lg) + c, g < NT >> lg.  Same outputs, except that H holds
-// the heavy bins in an unspecified order.  Each thread's heavy keys go to hk
-// at its exclusive-sum offset; a heavy key's class rank counts the heavier
-// keys in the hk ranges of the threads of its class.
+// emit_heavy for keys held in registers: each thread holds up to NK keys
+// (slot q valid when bit q of `valid` is set) as hi[q] = key >> 32 and lo(q),
+// the low half, computed on demand; the class of a key is its bin
+// mod s1, and ct.count threads ct(c, i) hold every key of class c (they may
+// hold keys of other classes too).  Same outputs as emit_heavy, except that
+// H holds the heavy bins in an unspecified order.  Each thread's heavy keys
+// go to hk at its exclusive-sum offset; a heavy key's class rank counts the
+// heavier keys of its class in the hk ranges of the threads of its class.
 // offs: LDS int32[2 NT]; part: LDS int32[NT / 64]; hk: LDS uint64[T];
 // cl: LDS int32[s1 * depth].
-template <int NT, int NK>
-__device__ void emit_heavy_regs(const uint64_t (&key)[NK], uint64_t valid, int c, int lg, int T, int depth,
+template <int NT, int NK, class LoF, class ClassThreads>
+__device__ void emit_heavy_regs(const uint32_t (&hi)[NK], uint64_t valid, LoF lo, ClassThreads ct, int lg, int T,
+                                int depth,
                                 uint64_t thr, uint64_t* hk, int32_t* offs, int32_t* part, int32_t* cl,
                                 GLOBAL int32_t* __restrict__ H, GLOBAL uint64_t* __restrict__ thr_out,
                                 GLOBAL int32_t* __restrict__ CL) {
@@ -663,10 +680,11 @@ __device__ void emit_heavy_regs(const uint64_t (&key)[NK], uint64_t valid, int c
     if (tid == 0) *thr_out = thr;
     for (int i = tid; i < s1 * depth; i += NT) cl[i] = -1;
     static_assert(NK <= 64, "slot mask");
+    const uint32_t thi = (uint32_t)(thr >> 32), tlo = (uint32_t)thr;
     uint64_t hm = 0;
 #pragma unroll
     for (int q = 0; q < NK; ++q)
-        if (((valid >> q) & 1) && key[q] >= thr) hm |= (uint64_t)1 << q;
+        if (((valid >> q) & 1) && (hi[q] > thi || (hi[q] == thi && lo(q) >= tlo))) hm |= (uint64_t)1 << q;
     const int cnt = __popcll(hm);
     const int ex = block_exclusive_sum<NT>(cnt, part);
     offs[tid] = ex;
@@ -676,24 +694,30 @@ __device__ void emit_heavy_regs(const uint64_t (&key)[NK], uint64_t valid, int c
     for (int q = 0; q < NK; ++q) {
         if ((hm >> q) & 1) {
             if (e < T) {
-                hk[e] = key[q];
-                H[e] = (int32_t)(0xffffffffu - (uint32_t)(key[q] & 0xffffffffu));
+                const uint32_t l = lo(q);
+                hk[e] = ((uint64_t)hi[q] << 32) | l;
+                H[e] = (int32_t)(0xffffffffu - l);
             }
             ++e;
         }
     }
     __syncthreads();
-    const int ng = NT >> lg;
+    const uint32_t cmask = (uint32_t)s1 - 1;
     for (int e1 = ex; e1 < min(ex + cnt, T); ++e1) {
         const uint64_t k = hk[e1];
+        const uint32_t hb = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
+        const int c = (int)(hb & cmask);
         int r = 0;
-        for (int g2 = 0; g2 < ng; ++g2) {
-            const int t2 = (g2 << lg) + c;
+        for (int i = 0; i < ct.count; ++i) {
+            const int t2 = ct(c, i);
             const int o2 = offs[t2];
             const int o3 = min(o2 + offs[NT + t2], T);
-            for (int e2 = o2; e2 < o3; ++e2) r += hk[e2] > k ? 1 : 0;
+            for (int e2 = o2; e2 < o3; ++e2) {
+                const uint64_t k2 = hk[e2];
+                r += (k2 > k && ((0xffffffffu - (uint32_t)(k2 & 0xffffffffu)) & cmask) == (uint32_t)c) ? 1 : 0;
+            }
         }
-        if (r < depth) cl[c * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+        if (r < depth) cl[c * depth + r] = (int32_t)hb;
     }
     __syncthreads();
     for (int i = tid; i < s1 * depth; i += NT) CL[i] = cl[i];
@@ -701,15 +725,106 @@ __device__ void emit_heavy_regs(const uint64_t (&key)[NK], uint64_t valid, int c
 
 static_assert(2 * kDftThreads <= kSelBins, "emit_heavy_regs offsets live in the histogram");
 
-// One workgroup per (modulus j, band b); the whole block in LDS.  Requires
-// s1 <= kDftThreads and ceil(h / (kDftThreads / s1)) <= KBMAX, h = (p-1)/2
-// (KBMAX = 8 keeps two workgroups per CU; 16 serves s1 = 256).
-// Step B runs one work item per thread (output group g = tid / s1 of column
-// c = tid mod s1); the results are written to E and their selection keys stay
-// in registers for the selection (slots 2 kk and 2 kk + 1: rows k0 + kk and
-// p - k0 - kk; slot 2 KBMAX: row 0, group 0 only).
-template <int KBMAX>
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+// The value held by lane l ^ 1 (DPP quad permutation 1, 0, 3, 2); every lane
+// of the wave must be active.
+__device__ __forceinline__ float lane_pair(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Step B on the matrix cores.  Real form of the p-point step: N = 2 c + part
+// indexes the real (part 0) and imaginary (part 1) planes of the [p][s1]
+// block, a_n = x_n + x_{p-n}, b_n = x_n - x_{p-n}, and for k = 0..h
+//   Cm[k][N] = sum_{n=1..h} cos(2 pi n k / p) a_n[N],
+//   Dm[k][N] = sum_{n=1..h} sin(2 pi n k / p) b_n[N]
+// (row k = 0 of the cosine matrix is all ones: Cm[0] = sum_n a_n).  Tiles are
+// FP32 16x16x4 MFMAs: M = 16 values of k, N = 16 floats (8 columns), K = 4
+// values of n.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// receives D[4 (l / 16) + r][l % 16] in register r.  Wave w owns the N-tiles
+// w + 8 t (t < ntw = s1 / 64) and the M-tiles m < mt = ceil((h + 1) / 16)
+// (at most NTW and MT).  bf: the block as floats.
+template <int MT, int NTW>
+__device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, int mt, int ntw, const float2* trig,
+                                         mf4 (&Cm)[NTW][MT], mf4 (&Dm)[NTW][MT]) {
+    const int lane = (int)threadIdx.x & 63;
+    const int wid = (int)threadIdx.x >> 6;
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+    const int rs = 2 * s1;   // floats per row
+#pragma unroll
+    for (int t = 0; t < NTW; ++t)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            Cm[t][m] = mf4{0.f, 0.f, 0.f, 0.f};
+            Dm[t][m] = mf4{0.f, 0.f, 0.f, 0.f};
+        }
+    const int steps = (h + 3) >> 2;
+    for (int st = 0; st < steps; ++st) {
+        const int n = 1 + 4 * st + lk;   // the K index this lane supplies
+        const bool nin = n <= h;
+        float ca[MT], sn[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int k = 16 * m + li;   // k > h on M-tiles m >= mt: zero
+            ca[m] = 0.f;
+            sn[m] = 0.f;
+            if (nin && k >= 1 && k <= h) {
+                const float2 tv = trig[(n - 1) * h + (k - 1)];
+                ca[m] = tv.x;
+                sn[m] = tv.y;
+            } else if (nin && k == 0) {
+                ca[m] = 1.f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            if (t >= ntw) break;
+            const int N = 16 * (wid + 8 * t) + li;
+            float av = 0.f, bv = 0.f;
+            if (nin) {
+                const float xa = bf[n * rs + N];
+                const float xb = bf[(p - n) * rs + N];
+                av = xa + xb;
+                bv = xa - xb;
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if (m >= mt) break;
+                Cm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[m], av, Cm[t][m], 0, 0, 0);
+                Dm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(sn[m], bv, Dm[t][m], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Threads of the VALU step B holding residue class c: (i << lg) + c.
+struct ValuClassThreads {
+    int count, lg;
+    __device__ int operator()(int c, int i) const { return (i << lg) + c; }
+};
+// Threads of the MFMA step B holding residue class c: N-tile c / 8 (wave
+// (c / 8) mod 8), lanes 16 lk + 2 (c mod 8) + part.
+struct MfmaClassThreads {
+    int count;   // 8
+    __device__ int operator()(int c, int i) const { return 64 * ((c >> 3) & 7) + 16 * (i >> 1) + 2 * (c & 7) + (i & 1); }
+};
+
+// One workgroup per (modulus j, band b); the whole block in LDS.
+// MT == 0: step B on the vector ALUs.  Requires s1 <= kDftThreads and
+// ceil(h / (kDftThreads / s1)) <= KBMAX, h = (p-1)/2 (KBMAX = 8 keeps two
+// workgroups per CU; 16 serves s1 = 256).  One work item per thread (output
+// group g = tid / s1 of column c = tid mod s1); the results are written to E
+// and their selection keys stay in registers (slots 2 kk and 2 kk + 1: rows
+// k0 + kk and p - k0 - kk; slot 2 KBMAX: row 0, group 0 only).
+// MX: step B on the matrix cores (pfa_mfma, up to MT = NTW = 2).  Requires
+// s1 = 64 or 128 and h + 1 <= 32 for every modulus.  Slot (t MT + m) 4 + r
+// holds the key of row k = 16 m + 4 (l / 16) + r of N-tile w + 8 t: X_k in
+// even lanes, X_{p-k} in odd lanes (row 0 in even lanes only).
+template <int KBMAX, bool MX>
 __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
+    constexpr int MT = MX ? 2 : 0;
+    constexpr int NTW = 2;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = kDftThreads;
     const Where at = locate(a);
@@ -745,6 +860,62 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     fft_rows_lds<NT>(buf, p, s1, lg, tw);
 
     // step B
+    GLOBAL float2* __restrict__ E = glb(io.E) + base;
+    const float scale = 1.0f / (float)P;
+    const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
+    const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
+    constexpr int NK = MT > 0 ? NTW * MT * 4 : 2 * KBMAX + 1;
+    uint32_t hi[NK];   // selection keys: |E|^2 bits; the low halves (2^32 - 1 - h) come from pos_of
+    uint64_t valid = 0;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+    const int plane = li & 1;   // 0: real, 1: imaginary plane (MFMA step B)
+    if constexpr (MT > 0) {
+        mf4 Cm[NTW][MT], Dm[NTW][MT];
+        const float* bf = reinterpret_cast<const float*>(buf);
+        const int mt = (h + 16) >> 4;
+        const int ntw = s1 >> 6;
+        pfa_mfma<MT, NTW>(bf, s1, p, h, mt, ntw, trig, Cm, Dm);
+        GLOBAL float* __restrict__ Ef = reinterpret_cast<GLOBAL float*>(E);
+        const float sgn = plane ? -1.f : 1.f;
+        const uint32_t pofs = (uint32_t)p << (lg + 1);   // float offset of row p
+#pragma unroll
+        for (int q = 0; q < NK; ++q) hi[q] = 0;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            if (t >= ntw) break;
+            const int N = 16 * (wid + 8 * t) + li;
+            const int c = N >> 1;
+            const float x0v = bf[N];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if (m >= mt) break;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q = (t * MT + m) * 4 + r;
+                    const int k = 16 * m + 4 * lk + r;
+                    const float cv = Cm[t][m][r];
+                    const float dp = lane_pair(Dm[t][m][r]);
+                    const float xk = (x0v + cv + sgn * dp) * scale;
+                    const float xm = (x0v + cv - sgn * dp) * scale;
+                    const float xk2 = lane_pair(xk);
+                    const float xm2 = lane_pair(xm);
+                    // even lanes key X_k = (xk, xk2), odd lanes X_{p-k} = (xm2, xm)
+                    const float re = plane ? xm2 : xk;
+                    const float im = plane ? xm : xk2;
+                    hi[q] = __float_as_uint(fmaf(re, re, im * im));
+                    if (k <= h) {
+                        const uint32_t ok = ((uint32_t)k << (lg + 1)) + (uint32_t)N;
+                        Ef[ok] = xk;
+                        if (k >= 1) Ef[pofs - ((uint32_t)k << (lg + 1)) + (uint32_t)N] = xm;
+                        if (plane == 0 || k >= 1) valid |= (uint64_t)1 << q;
+                    }
+                }
+            }
+        }
+    } else {
     const int ng = NT >> lg;
     const int KB = (h + ng - 1) / ng;
     const int g = tid >> lg;
@@ -753,45 +924,65 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const float2 x0 = buf[c];
     float2 C[KBMAX], D[KBMAX], sa;
     pfa_column_sums<KBMAX>(buf, s1, c, p, h, k0, KB, trig, C, D, sa);
-    GLOBAL float2* __restrict__ E = glb(io.E) + base;
-    const float scale = 1.0f / (float)P;
-    const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
-    const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
-    constexpr int NK = 2 * KBMAX + 1;
-    uint64_t key[NK];
-    uint64_t valid = 0;
 #pragma unroll
     for (int kk = 0; kk < KBMAX; ++kk) {
         const int k = k0 + kk;
-        key[2 * kk] = key[2 * kk + 1] = 0;
+        hi[2 * kk] = hi[2 * kk + 1] = 0;
         if (kk < KB && k <= h) {
             const float2 xk = make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale);
             const float2 xm = make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale);
-            const int ik = (k << lg) + c;
-            const int im = ((p - k) << lg) + c;
-            st2(E + ik, xk);
-            st2(E + im, xm);
-            key[2 * kk] = value_key(xk, pfa_bin(ik, lg, s1, (uint32_t)P, cA, cB));
-            key[2 * kk + 1] = value_key(xm, pfa_bin(im, lg, s1, (uint32_t)P, cA, cB));
+            st2(E + (k << lg) + c, xk);
+            st2(E + ((p - k) << lg) + c, xm);
+            hi[2 * kk] = __float_as_uint(fmaf(xk.x, xk.x, xk.y * xk.y));
+            hi[2 * kk + 1] = __float_as_uint(fmaf(xm.x, xm.x, xm.y * xm.y));
             valid |= (uint64_t)3 << (2 * kk);
         }
     }
-    key[NK - 1] = 0;
+    hi[NK - 1] = 0;
     if (g == 0) {
         const float2 xz = make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale);
         st2(E + c, xz);
-        key[NK - 1] = value_key(xz, pfa_bin(c, lg, s1, (uint32_t)P, cA, cB));
+        hi[NK - 1] = __float_as_uint(fmaf(xz.x, xz.x, xz.y * xz.y));
         valid |= (uint64_t)1 << (NK - 1);
     }
+    }
+    // Good-Thomas position of slot q (q a compile-time constant after unrolling)
+    // of thread th
+    auto pos_of = [&](int q, int th) -> int {
+        if constexpr (MT > 0) {
+            const int t = q / (MT * 4);
+            const int k = 16 * ((q >> 2) % MT) + 4 * ((th >> 4) & 3) + (q & 3);
+            const int c = (16 * ((th >> 6) + 8 * t) + (th & 15)) >> 1;
+            return (((th & 1) ? p - k : k) << lg) + c;
+        } else {
+            const int c = th & (s1 - 1);
+            if (q == NK - 1) return c;
+            const int ng = NT >> lg;
+            const int k = 1 + (th >> lg) * ((h + ng - 1) / ng) + (q >> 1);
+            return (((q & 1) ? p - k : k) << lg) + c;
+        }
+    };
+    // The thread index passes through an empty asm so that the position
+    // arithmetic stays where a low half is needed (rarely) instead of being
+    // hoisted and held in registers for every slot.
+    auto lo_of = [&](int q) -> uint32_t {
+        int th = tid;
+        asm volatile("" : "+v"(th));
+        return 0xffffffffu - pfa_bin(pos_of(q, th), lg, s1, (uint32_t)P, cA, cB);
+    };
     auto each = [&](auto f) {
 #pragma unroll
         for (int q = 0; q < NK; ++q)
-            if ((valid >> q) & 1) f(key[q]);
+            if ((valid >> q) & 1) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q); });
     };
     const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy_regs<NT, NK>(key, valid, c, lg, d->T, d->depth, thr, hk, hist, part, cl, glb(io.H) + blk * d->T,
-                            glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
+    auto emit = [&](auto ct) {
+        emit_heavy_regs<NT, NK>(hi, valid, lo_of, ct, lg, d->T, d->depth, thr, hk, hist, part, cl,
+                                glb(io.H) + blk * d->T, glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
+    };
+    if constexpr (MT > 0) emit(MfmaClassThreads{8});
+    else emit(ValuClassThreads{NT >> lg, lg});
 }
 
 // Split path, step A: block -> (modulus j, band b, chunk of rows_per rows).
@@ -906,7 +1097,10 @@ __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
     const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
     auto kf = [&](int i) { return value_key(ld2(E + i), pfa_bin(i, lg, s1, (uint32_t)P, cA, cB)); };
     auto each = [&](auto f) {
-        for (int i = (int)threadIdx.x; i < P; i += kThreads) f(kf(i));
+        for (int i = (int)threadIdx.x; i < P; i += kThreads) {
+            const uint64_t k = kf(i);
+            f((uint32_t)(k >> 32), [k] { return k; });
+        }
     };
     const uint64_t thr = kth_largest<kThreads>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
@@ -1259,8 +1453,9 @@ size_t select_lds_bytes(const SigDesc& d) {
 // for an opt-in.  A rejected request is not an error here: the launch itself
 // reports a size the device cannot hold.
 hipError_t configure_kernels(int max_lds) {
-    const void* ks[7] = {(const void*)k_dft<8>, (const void*)k_dft<16>, (const void*)k_identify, (const void*)k_merge,
-                         (const void*)k_dft_rows, (const void*)k_dft_cols, (const void*)k_select};
+    const void* ks[8] = {(const void*)k_dft<8, false>, (const void*)k_dft<16, false>, (const void*)k_dft<0, true>,
+                         (const void*)k_identify, (const void*)k_merge, (const void*)k_dft_rows,
+                         (const void*)k_dft_cols, (const void*)k_select};
     for (const void* k : ks) {
         hipFuncAttributes fa;
         int static_lds = 0;
@@ -1283,8 +1478,15 @@ hipError_t launch_gather(const BatchArgs& a, int blocks, int taps, hipStream_t s
 hipError_t launch_dft(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
     // lds carries the byte count in its low 32 bits and the output-pair bound above them
     const size_t bytes = lds & 0xffffffffu;
-    if ((lds >> 32) > 8) hipLaunchKernelGGL(k_dft<16>, dim3(blocks), dim3(kDftThreads), bytes, st, a);
-    else hipLaunchKernelGGL(k_dft<8>, dim3(blocks), dim3(kDftThreads), bytes, st, a);
+    const int pairs = (int)(lds >> 32);
+    const dim3 g(blocks), t(kDftThreads);
+    if (pairs > 8) hipLaunchKernelGGL((k_dft<16, false>), g, t, bytes, st, a);
+    else hipLaunchKernelGGL((k_dft<8, false>), g, t, bytes, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((k_dft<0, true>), dim3(blocks), dim3(kDftThreads), lds, st, a);
     return hipGetLastError();
 }
 

@@ -240,4 +240,12 @@ int dft_pairs_per_thread(const SigDesc& d) {
 
 bool dft_fits_one_workgroup(const SigDesc& d) { return dft_pairs_per_thread(d) <= kDftKBMax; }
 
+int dft_mfma_variant(const SigDesc& d) {
+    static_assert(kDftThreads == 512, "the matrix-core step B assumes 8 waves");
+    const int ntw = d.s1 == 64 ? 1 : d.s1 == 128 ? 2 : 0;
+    const int rows = (d.p[d.K - 1] - 1) / 2 + 1;   // k = 0..h of the largest prime
+    const int mt = rows <= 16 ? 1 : rows <= 32 ? 2 : 0;
+    return ntw && mt ? mt * 4 + ntw : 0;
+}
+
 }  // namespace sft

@@ -103,6 +103,9 @@ WorkspaceLayout workspace_layout(const sft_plan_info& info);
 size_t dft_lds_bytes(const SigDesc& d);
 bool dft_fits_one_workgroup(const SigDesc& d);   // the in-LDS short-DFT kernel's shape limits
 int dft_pairs_per_thread(const SigDesc& d);
+// Whether the in-LDS kernel's matrix-core step B covers the plan (s1 = 64 NTW, h + 1 <= 16 MT, NTW, MT <= 2):
+// MT * 4 + NTW, else 0.
+int dft_mfma_variant(const SigDesc& d);
 
 // kernels.hip: host-side launchers (enqueue only).  Block counts per signal:
 int gather_blocks(const SigDesc& d);
@@ -121,6 +124,7 @@ size_t rows_lds_bytes(const SigDesc& d);
 size_t cols_lds_bytes(const SigDesc& d);
 size_t select_lds_bytes(const SigDesc& d);
 hipError_t launch_dft_rows(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_dft_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_dft_cols(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_merge(const BatchArgs& a, int blocks, hipStream_t st);

@@ -68,6 +68,8 @@ INTERMEDIATE_CASES = [
     ("n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2}, 3),
     ("n31_s1", 31, 1, None, {}, 4),
     ("n64_s64", 64, 64, None, {}, 5),
+    ("mx_n2e16_s40_10db", 2 ** 16, 40, 10.0, {"dft_path": 3}, 6),
+    ("valu_n2e16_s40_10db", 2 ** 16, 40, 10.0, {"dft_path": 1}, 6),
     ("split_prime_n100003_s20_30db", 100_003, 20, 30.0, {"dft_path": 2}, 1),
     ("split_n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2, "dft_path": 2}, 3),
 ]
