@@ -660,52 +660,60 @@ __device__ void emit_heavy(KeyF key, int P, int T, int s1, int depth, uint64_t t
 }
 
 // emit_heavy for keys held in registers: each thread holds up to NK keys
-// (slot q valid when bit q of `valid` is set) as hi[q] = key >> 32 and lo(q),
-// the low half, computed on demand; the class of a key is its bin
-// mod s1, and ct.count threads ct(c, i) hold every key of class c (they may
-// hold keys of other classes too).  Same outputs as emit_heavy, except that
-// H holds the heavy bins in an unspecified order.  Each thread's heavy keys
-// go to hk at its exclusive-sum offset; a heavy key's class rank counts the
-// heavier keys of its class in the hk ranges of the threads of its class.
+// (slot q valid when bit q of `valid` is set) as hi[q] = key >> 32; the low
+// half lo(q, th) of slot q of thread th is computed on demand (q may be a
+// run-time value there).  The class of a key is its bin mod s1, and
+// ct.count threads ct(c, i) hold every key of class c (they may hold keys of
+// other classes too).  Same outputs as emit_heavy, except that H holds the
+// heavy bins in an unspecified order.  Each thread's heavy slots go to hk at
+// its exclusive-sum offset as (hi, thread, slot); thread e then completes
+// entry e (its bin) and ranks it within its class against the entries of
+// the threads of that class.
 // offs: LDS int32[2 NT]; part: LDS int32[NT / 64]; hk: LDS uint64[T];
 // cl: LDS int32[s1 * depth].
 template <int NT, int NK, class LoF, class ClassThreads>
 __device__ void emit_heavy_regs(const uint32_t (&hi)[NK], uint64_t valid, LoF lo, ClassThreads ct, int lg, int T,
-                                int depth,
-                                uint64_t thr, uint64_t* hk, int32_t* offs, int32_t* part, int32_t* cl,
+                                int depth, uint64_t thr, uint64_t* hk, int32_t* offs, int32_t* part, int32_t* cl,
                                 GLOBAL int32_t* __restrict__ H, GLOBAL uint64_t* __restrict__ thr_out,
                                 GLOBAL int32_t* __restrict__ CL) {
+    static_assert(NK <= 64 && NT <= (1 << 24), "slot and thread fields");
     const int tid = (int)threadIdx.x;
     const int s1 = 1 << lg;
     if (tid == 0) *thr_out = thr;
     for (int i = tid; i < s1 * depth; i += NT) cl[i] = -1;
-    static_assert(NK <= 64, "slot mask");
     const uint32_t thi = (uint32_t)(thr >> 32), tlo = (uint32_t)thr;
     uint64_t hm = 0;
 #pragma unroll
-    for (int q = 0; q < NK; ++q)
-        if (((valid >> q) & 1) && (hi[q] > thi || (hi[q] == thi && lo(q) >= tlo))) hm |= (uint64_t)1 << q;
+    for (int q = 0; q < NK; ++q) {
+        if ((valid >> q) & 1) {
+            if (hi[q] > thi) hm |= (uint64_t)1 << q;
+            else if (hi[q] == thi && lo(q, tid) >= tlo) hm |= (uint64_t)1 << q;   // ties on |E|^2: rare
+        }
+    }
     const int cnt = __popcll(hm);
     const int ex = block_exclusive_sum<NT>(cnt, part);
     offs[tid] = ex;
     offs[NT + tid] = cnt;
-    int e = ex;
 #pragma unroll
     for (int q = 0; q < NK; ++q) {
         if ((hm >> q) & 1) {
-            if (e < T) {
-                const uint32_t l = lo(q);
-                hk[e] = ((uint64_t)hi[q] << 32) | l;
-                H[e] = (int32_t)(0xffffffffu - l);
-            }
-            ++e;
+            const int e = ex + __popcll(hm & (((uint64_t)1 << q) - 1));
+            if (e < T) hk[e] = ((uint64_t)hi[q] << 32) | (uint32_t)((tid << 6) | q);
         }
     }
     __syncthreads();
+    const int n = min(offs[NT - 1] + offs[2 * NT - 1], T);
+    for (int e = tid; e < n; e += NT) {   // entry e is read and rewritten by this thread only
+        const uint64_t v = hk[e];
+        const uint32_t l = lo((int)(v & 63), (int)((uint32_t)v >> 6));
+        hk[e] = (v & 0xffffffff00000000ull) | l;
+        H[e] = (int32_t)(0xffffffffu - l);
+    }
+    __syncthreads();
     const uint32_t cmask = (uint32_t)s1 - 1;
-    for (int e1 = ex; e1 < min(ex + cnt, T); ++e1) {
-        const uint64_t k = hk[e1];
-        const uint32_t hb = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
+    for (int e = tid; e < n; e += NT) {
+        const uint64_t mine = hk[e];
+        const uint32_t hb = 0xffffffffu - (uint32_t)(mine & 0xffffffffu);
         const int c = (int)(hb & cmask);
         int r = 0;
         for (int i = 0; i < ct.count; ++i) {
@@ -714,7 +722,7 @@ __device__ void emit_heavy_regs(const uint32_t (&hi)[NK], uint64_t valid, LoF lo
             const int o3 = min(o2 + offs[NT + t2], T);
             for (int e2 = o2; e2 < o3; ++e2) {
                 const uint64_t k2 = hk[e2];
-                r += (k2 > k && ((0xffffffffu - (uint32_t)(k2 & 0xffffffffu)) & cmask) == (uint32_t)c) ? 1 : 0;
+                r += (k2 > mine && ((0xffffffffu - (uint32_t)(k2 & 0xffffffffu)) & cmask) == (uint32_t)c) ? 1 : 0;
             }
         }
         if (r < depth) cl[c * depth + r] = (int32_t)hb;
@@ -946,8 +954,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         valid |= (uint64_t)1 << (NK - 1);
     }
     }
-    // Good-Thomas position of slot q (q a compile-time constant after unrolling)
-    // of thread th
+    // Good-Thomas position of slot q of thread th
     auto pos_of = [&](int q, int th) -> int {
         if constexpr (MT > 0) {
             const int t = q / (MT * 4);
@@ -964,16 +971,15 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     };
     // The thread index passes through an empty asm so that the position
     // arithmetic stays where a low half is needed (rarely) instead of being
-    // hoisted and held in registers for every slot.
-    auto lo_of = [&](int q) -> uint32_t {
-        int th = tid;
+    // hoisted or speculated and held in registers for every slot.
+    auto lo_of = [&](int q, int th) -> uint32_t {
         asm volatile("" : "+v"(th));
         return 0xffffffffu - pfa_bin(pos_of(q, th), lg, s1, (uint32_t)P, cA, cB);
     };
     auto each = [&](auto f) {
 #pragma unroll
         for (int q = 0; q < NK; ++q)
-            if ((valid >> q) & 1) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q); });
+            if ((valid >> q) & 1) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q, tid); });
     };
     const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
