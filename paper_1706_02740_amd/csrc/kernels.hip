@@ -376,6 +376,136 @@ __device__ void fft_rows_lds(float2* buf, int rows, int s1, int lg, const float2
     }
 }
 
+// ---- in-register DFTs of length R <= 16 (natural order in and out)
+// cos and sin of 2 pi k / 16
+__constant__ const float kCos16[16] = {1.000000000f, 0.923879533f, 0.707106781f, 0.382683432f, 0.000000000f, -0.382683432f, -0.707106781f, -0.923879533f, -1.000000000f, -0.923879533f, -0.707106781f, -0.382683432f, -0.000000000f, 0.382683432f, 0.707106781f, 0.923879533f};
+__constant__ const float kSin16[16] = {0.000000000f, 0.382683432f, 0.707106781f, 0.923879533f, 1.000000000f, 0.923879533f, 0.707106781f, 0.382683432f, 0.000000000f, -0.382683432f, -0.707106781f, -0.923879533f, -1.000000000f, -0.923879533f, -0.707106781f, -0.382683432f};
+
+constexpr int brev_const(int i, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+constexpr int log2_const(int r) { return r <= 1 ? 0 : 1 + log2_const(r / 2); }
+
+// v <- DFT_R(v): X_k = sum_n v_n exp(-2 pi i n k / R), radix-2 decimation in
+// time with compile-time twiddles (the bit reversal is a register renaming).
+template <int R>
+__device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
+    static_assert(R >= 2 && R <= 16 && (R & (R - 1)) == 0, "radix");
+    constexpr int LG = log2_const(R);
+    float2 t[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) t[brev_const(i, LG)] = v[i];
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int s0 = 0; s0 < R; s0 += len)
+#pragma unroll
+            for (int k = 0; k < half; ++k) {
+                const int e = k * (16 / len);   // W_len^k = W_16^e
+                float2 b = t[s0 + k + half];
+                if (e == 4) {
+                    b = make_float2(b.y, -b.x);
+                } else if (e != 0) {
+                    const float c = kCos16[e], sn = kSin16[e];
+                    b = make_float2(fmaf(b.x, c, b.y * sn), fmaf(b.y, c, -b.x * sn));
+                }
+                const float2 a0 = t[s0 + k];
+                t[s0 + k] = make_float2(a0.x + b.x, a0.y + b.y);
+                t[s0 + k + half] = make_float2(a0.x - b.x, a0.y - b.y);
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = t[i];
+}
+
+// Length-S FFTs (S = R1 R2) of `rows` <= ROWSMAX rows in LDS, two passes
+// through registers with n = n1 + R1 n2 and k = R2 k1 + k2:
+//   Z[n1][k2]     = W_S^(n1 k2) sum_n2 x[n1 + R1 n2] W_R2^(n2 k2)
+//   X[R2 k1 + k2] = sum_n1 Z[n1][k2] W_R1^(n1 k1)
+// Z sits in the row at k2 R1 + (n1 ^ f), f = (k2 + R2 (row & 1)) mod R1, so
+// that pass 2 reads R1 values per thread without LDS bank conflicts.
+// tw: LDS exp(-2 pi i m / S), m < S.
+template <int NT, int R1, int R2, int ROWSMAX>
+__device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
+    constexpr int S = R1 * R2;
+    constexpr int IT1 = (ROWSMAX * R1 + NT - 1) / NT;
+    constexpr int IT2 = (ROWSMAX * R2 + NT - 1) / NT;
+    constexpr int L1 = log2_const(R1), L2 = log2_const(R2);
+    const int tid = (int)threadIdx.x;
+    float2 z[IT1][R2];
+#pragma unroll
+    for (int it = 0; it < IT1; ++it) {
+        const int item = tid + it * NT;
+        if (item < rows * R1) {
+            const int row = item >> L1;
+            const int n1 = item & (R1 - 1);
+            const float2* x = buf + row * S + n1;
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) z[it][n2] = x[n2 * R1];
+            dft_reg<R2>(z[it]);
+#pragma unroll
+            for (int k2 = 1; k2 < R2; ++k2) {
+                const float2 w = tw[n1 * k2];
+                const float2 b = z[it][k2];
+                z[it][k2] = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT1; ++it) {
+        const int item = tid + it * NT;
+        if (item < rows * R1) {
+            const int row = item >> L1;
+            const int n1 = item & (R1 - 1);
+            float2* zr = buf + row * S;
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) zr[k2 * R1 + (n1 ^ ((k2 + R2 * (row & 1)) & (R1 - 1)))] = z[it][k2];
+        }
+    }
+    __syncthreads();
+    float2 y[IT2][R1];
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+        const int item = tid + it * NT;
+        if (item < rows * R2) {
+            const int row = item >> L2;
+            const int k2 = item & (R2 - 1);
+            const int f = (k2 + R2 * (row & 1)) & (R1 - 1);
+            const float2* zr = buf + row * S + k2 * R1;
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) y[it][n1] = zr[n1 ^ f];
+            dft_reg<R1>(y[it]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+        const int item = tid + it * NT;
+        if (item < rows * R2) {
+            const int row = item >> L2;
+            const int k2 = item & (R2 - 1);
+            float2* xr = buf + row * S + k2;
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) xr[k1 * R2] = y[it][k1];
+        }
+    }
+    __syncthreads();
+}
+
+// Row FFTs: two register passes for s1 = 64 and 128 (at most ROWS128 and
+// ROWS64 rows), else the radix-2/4 LDS passes.  The in-LDS and the split
+// kernels take the same branch for a plan, so their results stay bitwise equal.
+template <int NT, int ROWS128, int ROWS64>
+__device__ __forceinline__ void fft_rows(float2* buf, int rows, int s1, int lg, const float2* tw) {
+    if (s1 == 128 && rows <= ROWS128) fft_rows_2pass<NT, 16, 8, ROWS128>(buf, rows, tw);
+    else if (s1 == 64 && rows <= ROWS64) fft_rows_2pass<NT, 8, 8, ROWS64>(buf, rows, tw);
+    else fft_rows_lds<NT>(buf, rows, s1, lg, tw);
+}
+
 // Cosine/sine table of a p-point step (host-computed per modulus), copied to
 // LDS: trig[(n - 1) h + (k - 1)] = (cos, sin)(2 pi (n k mod p) / p), n, k in [1, h].
 template <int NT>
@@ -853,8 +983,8 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
 
     float2* buf = reinterpret_cast<float2*>(smem);
-    float2* tw = reinterpret_cast<float2*>(smem + (size_t)Pmax * 8);
-    float2* trig = tw + (s1 >> 1);
+    float2* tw = reinterpret_cast<float2*>(smem + (size_t)Pmax * 8);   // [s1]
+    float2* trig = tw + s1;
     int32_t* hist = reinterpret_cast<int32_t*>(trig + hmax * hmax);
     int32_t* part = hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [T]
@@ -862,10 +992,14 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
 
     const GLOBAL float2* __restrict__ S = glb(io.S) + base;
     copy_to_lds<NT, 8>(buf, S, P);
-    for (int i = tid; i < (s1 >> 1); i += NT) tw[i] = ld2(glb(d->tw_s1) + i);
+    for (int i = tid; i < (s1 >> 1); i += NT) {   // the full circle: W^(m + s1/2) = -W^m
+        const float2 w = ld2(glb(d->tw_s1) + i);
+        tw[i] = w;
+        tw[i + (s1 >> 1)] = make_float2(-w.x, -w.y);
+    }
     load_trig<NT>(trig, h, glb(d->trig) + d->trig_off[j]);
     __syncthreads();
-    fft_rows_lds<NT>(buf, p, s1, lg, tw);
+    fft_rows<NT, 64, 64>(buf, p, s1, lg, tw);
 
     // step B
     GLOBAL float2* __restrict__ E = glb(io.E) + base;
@@ -1027,9 +1161,18 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     const int n = rows << lg;
     const GLOBAL float2* __restrict__ S = glb(io.S) + base;
     copy_to_lds<kThreads, 8>(buf, S, n);
-    for (int i = tid; i < (s1 >> 1); i += kThreads) tw[i] = ld2(glb(d->tw_s1) + i);
+    for (int i = tid; i < (s1 >> 1); i += kThreads) {   // the full circle: W^(m + s1/2) = -W^m
+        const float2 w = ld2(glb(d->tw_s1) + i);
+        tw[i] = w;
+        tw[i + (s1 >> 1)] = make_float2(-w.x, -w.y);
+    }
     __syncthreads();
-    fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
+    // rows are transformed independently: take the in-LDS kernel's branch for
+    // this plan (two register passes when s1 is 64 or 128 and p <= 64)
+    if ((s1 == 128 || s1 == 64) && p <= 64)
+        fft_rows<kThreads, kRowElems / 128, kRowElems / 64>(buf, rows, s1, lg, tw);
+    else
+        fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
     GLOBAL float2* __restrict__ X = glb(io.E) + base;   // the bins' buffer holds the step-A result
     for (int i = tid; i < n; i += kThreads) st2(X + i, buf[i]);
 }
@@ -1443,7 +1586,7 @@ int select_blocks(const SigDesc& d) { return d.K * d.Q; }
 
 size_t rows_lds_bytes(const SigDesc& d) {
     const int rows_per = std::max(1, kRowElems >> d.log2s1);
-    return (size_t)rows_per * d.s1 * 8 + (size_t)(d.s1 / 2) * 8 + 64;
+    return (size_t)rows_per * d.s1 * 8 + (size_t)d.s1 * 8 + 64;
 }
 size_t cols_lds_bytes(const SigDesc& d) {
     int pmax = 0;

@@ -225,9 +225,9 @@ size_t dft_lds_bytes(const SigDesc& d) {
     for (int j = 0; j < d.K; ++j)
         if (d.P[j] > Pmax) Pmax = d.P[j];
     const size_t h = (size_t)(d.p[d.K - 1] - 1) / 2;
-    // data / keys (8 B per bin) + s1/2 twiddles + h^2 cos/sin pairs + histogram + scan partials
+    // data (8 B per bin) + s1 twiddles + h^2 cos/sin pairs + histogram + scan partials
     // + the T heavy keys + the class lists
-    return (size_t)Pmax * 8 + (size_t)(d.s1 / 2) * 8 + h * h * 8 + (size_t)kSelBins * 4 + 64 + (size_t)d.T * 8 +
+    return (size_t)Pmax * 8 + (size_t)d.s1 * 8 + h * h * 8 + (size_t)kSelBins * 4 + 64 + (size_t)d.T * 8 +
            (size_t)d.s1 * d.depth * 4 + 64;
 }
 
