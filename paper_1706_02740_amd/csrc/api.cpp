@@ -216,10 +216,28 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
                 trig[o] = make_float2((float)cos(ang), (float)sin(ang));
             }
     }
+    const size_t n_mxa = (size_t)d.K * kMxSteps * kMxTiles * 64;
+    std::vector<float2> mxa(n_mxa, make_float2(0.f, 0.f));
+    for (int j = 0; j < d.K; ++j) {
+        const int pj = d.p[j], hj = (pj - 1) / 2;
+        for (int st = 0; st < kMxSteps; ++st)
+            for (int m = 0; m < kMxTiles; ++m)
+                for (int l = 0; l < 64; ++l) {
+                    const int n = 1 + 4 * st + l / 16, k = 16 * m + l % 16;
+                    float2 v = make_float2(0.f, 0.f);
+                    if (n <= hj && k == 0) {
+                        v = make_float2(1.f, 0.f);
+                    } else if (n <= hj && k <= hj) {
+                        const double ang = 2.0 * M_PI * (double)((n * k) % pj) / (double)pj;
+                        v = make_float2((float)cos(ang), (float)sin(ang));
+                    }
+                    mxa[(((size_t)j * kMxSteps + st) * kMxTiles + m) * 64 + l] = v;
+                }
+    }
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al((size_t)Qpad * 4);
-    const size_t b_trig = al(n_trig * 8);
-    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig;
+    const size_t b_trig = al(n_trig * 8), b_mxa = al(n_mxa * 8);
+    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa;
     hipError_t e = hipMalloc(&pl->tables, tbytes);
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(tables) failed"); }
     char* tb = static_cast<char*>(pl->tables);
@@ -228,12 +246,15 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     d.tw_p = reinterpret_cast<const float2*>(tb + b_band + b_tws1);
     d.rate = reinterpret_cast<const float*>(tb + b_band + b_tws1 + b_twp);
     d.trig = reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate);
+    d.mxa = reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate + b_trig);
     e = hipMemcpy(tb, band.data(), n_band * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band, tws1.data(), n_tws1 * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1, twp.data(), n_twp * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1 + b_twp, rate.data(), (size_t)Qpad * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate, trig.data(), n_trig * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate + b_trig, mxa.data(), n_mxa * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(tables)"); }
     e = hipMalloc(&pl->ddesc, sizeof(SigDesc));
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(descriptor) failed"); }

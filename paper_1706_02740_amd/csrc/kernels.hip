@@ -882,9 +882,12 @@ __device__ __forceinline__ float lane_pair(float v) {
 // receives D[4 (l / 16) + r][l % 16] in register r.  Wave w owns the N-tiles
 // w + 8 t (t < ntw = s1 / 64) and the M-tiles m < mt = ceil((h + 1) / 16)
 // (at most NTW and MT).  bf: the block as floats.
+// At: the A operands in lane order ((st kMxTiles + m) 64 + lane, as the
+// plan's mxa table), in LDS.
 template <int MT, int NTW>
-__device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, int mt, int ntw, const float2* trig,
+__device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, int mt, int ntw, const float2* At,
                                          mf4 (&Cm)[NTW][MT], mf4 (&Dm)[NTW][MT]) {
+    static_assert(MT <= kMxTiles, "A operand tiles");
     const int lane = (int)threadIdx.x & 63;
     const int wid = (int)threadIdx.x >> 6;
     const int li = lane & 15;
@@ -901,36 +904,25 @@ __device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, 
     for (int st = 0; st < steps; ++st) {
         const int n = 1 + 4 * st + lk;   // the K index this lane supplies
         const bool nin = n <= h;
-        float ca[MT], sn[MT];
+        float2 av[MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int k = 16 * m + li;   // k > h on M-tiles m >= mt: zero
-            ca[m] = 0.f;
-            sn[m] = 0.f;
-            if (nin && k >= 1 && k <= h) {
-                const float2 tv = trig[(n - 1) * h + (k - 1)];
-                ca[m] = tv.x;
-                sn[m] = tv.y;
-            } else if (nin && k == 0) {
-                ca[m] = 1.f;
-            }
-        }
+        for (int m = 0; m < MT; ++m) av[m] = At[(st * kMxTiles + m) * 64 + lane];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             if (t >= ntw) break;
             const int N = 16 * (wid + 8 * t) + li;
-            float av = 0.f, bv = 0.f;
+            float a_n = 0.f, b_n = 0.f;
             if (nin) {
                 const float xa = bf[n * rs + N];
                 const float xb = bf[(p - n) * rs + N];
-                av = xa + xb;
-                bv = xa - xb;
+                a_n = xa + xb;
+                b_n = xa - xb;
             }
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 if (m >= mt) break;
-                Cm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[m], av, Cm[t][m], 0, 0, 0);
-                Dm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(sn[m], bv, Dm[t][m], 0, 0, 0);
+                Cm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m].x, a_n, Cm[t][m], 0, 0, 0);
+                Dm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m].y, b_n, Dm[t][m], 0, 0, 0);
             }
         }
     }
@@ -991,13 +983,30 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     int32_t* cl = reinterpret_cast<int32_t*>(hk + d->T);        // [s1 depth]
 
     const GLOBAL float2* __restrict__ S = glb(io.S) + base;
-    copy_to_lds<NT, 8>(buf, S, P);
-    for (int i = tid; i < (s1 >> 1); i += NT) {   // the full circle: W^(m + s1/2) = -W^m
-        const float2 w = ld2(glb(d->tw_s1) + i);
-        tw[i] = w;
-        tw[i + (s1 >> 1)] = make_float2(-w.x, -w.y);
+    if constexpr (MX) {
+        // every load of the block in flight at once: samples, twiddles, the
+        // p-point step's A operands (to LDS in place of the cosine/sine table)
+        static_assert(kMxSteps * kMxTiles * 64 == 2 * NT, "two A operands per thread");
+        float2 w = make_float2(0.f, 0.f);
+        if (tid < (s1 >> 1)) w = ld2(glb(d->tw_s1) + tid);
+        const GLOBAL float2* A = glb(d->mxa) + (size_t)j * kMxSteps * kMxTiles * 64;
+        const float2 a0 = ld2(A + tid), a1 = ld2(A + tid + NT);
+        copy_to_lds<NT, 8>(buf, S, P);
+        if (tid < (s1 >> 1)) {   // the full circle: W^(m + s1/2) = -W^m
+            tw[tid] = w;
+            tw[tid + (s1 >> 1)] = make_float2(-w.x, -w.y);
+        }
+        trig[tid] = a0;
+        trig[tid + NT] = a1;
+    } else {
+        copy_to_lds<NT, 8>(buf, S, P);
+        for (int i = tid; i < (s1 >> 1); i += NT) {   // the full circle: W^(m + s1/2) = -W^m
+            const float2 w = ld2(glb(d->tw_s1) + i);
+            tw[i] = w;
+            tw[i + (s1 >> 1)] = make_float2(-w.x, -w.y);
+        }
+        load_trig<NT>(trig, h, glb(d->trig) + d->trig_off[j]);
     }
-    load_trig<NT>(trig, h, glb(d->trig) + d->trig_off[j]);
     __syncthreads();
     fft_rows<NT, 64, 64>(buf, p, s1, lg, tw);
 

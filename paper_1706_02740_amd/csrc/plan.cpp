@@ -8,6 +8,7 @@
 //   steps, which balances the window-truncation and aliasing losses.
 //   Inner algorithm: s1 = least power of two >= 2 s, G = max(2, ceil(log2(N/s1)/6)),
 //   p_min^G s1 >= N, K = 2G + 1 odd primes >= max(3, p_min), P_j = s1 p_j.
+#include <algorithm>
 #include <math.h>
 #include <string.h>
 
@@ -225,9 +226,11 @@ size_t dft_lds_bytes(const SigDesc& d) {
     for (int j = 0; j < d.K; ++j)
         if (d.P[j] > Pmax) Pmax = d.P[j];
     const size_t h = (size_t)(d.p[d.K - 1] - 1) / 2;
-    // data (8 B per bin) + s1 twiddles + h^2 cos/sin pairs + histogram + scan partials
+    // the cosine/sine table, or the matrix-core step's A operands
+    const size_t ntrig = dft_mfma_variant(d) ? std::max(h * h, (size_t)kMxSteps * kMxTiles * 64) : h * h;
+    // data (8 B per bin) + s1 twiddles + the table + histogram + scan partials
     // + the T heavy keys + the class lists
-    return (size_t)Pmax * 8 + (size_t)d.s1 * 8 + h * h * 8 + (size_t)kSelBins * 4 + 64 + (size_t)d.T * 8 +
+    return (size_t)Pmax * 8 + (size_t)d.s1 * 8 + ntrig * 8 + (size_t)kSelBins * 4 + 64 + (size_t)d.T * 8 +
            (size_t)d.s1 * d.depth * 4 + 64;
 }
 

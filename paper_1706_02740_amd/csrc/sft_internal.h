@@ -19,6 +19,8 @@ constexpr int kRowElems = 4096;        // complex values per workgroup in the sp
 constexpr int kColChunk = 64;          // columns per workgroup in the split path's p-point DFTs
 constexpr int kMaxDepth = 8;           // class-list length bound (depth^G <= 64 with G >= 2)
 constexpr int kSelBins = 1024;         // buckets of one radix-select pass (10-bit digits)
+constexpr int kMxSteps = 8;            // K-steps (4 values of n each) of the matrix-core p-point step: h <= 32
+constexpr int kMxTiles = 2;            // M-tiles (16 values of k each): h + 1 <= 32
 constexpr int kDftKBMax = 16;          // p-point output pairs per thread in the in-LDS short-DFT kernel
 
 // Status bits written by the device.
@@ -59,6 +61,10 @@ struct SigDesc {
     const float* rate;       // [Q]: q_b / N, the per-node band phase rate in turns
     const float2* trig;      // concatenated [h_j^2]: (cos, sin)(2 pi (n k mod p_j) / p_j), n, k in [1, h_j]
     int32_t trig_off[kMaxK];
+    // [K][kMxSteps][kMxTiles][64]: the matrix-core step's A operands in lane order;
+    // lane l of step st, tile m: n = 1 + 4 st + l / 16, k = 16 m + l % 16 ->
+    // (cos, sin)(2 pi (n k mod p) / p) for n, k in [1, h]; (1, 0) for k = 0 < n <= h; else 0
+    const float2* mxa;
 };
 
 // Per-transform pointers: input, outputs and workspace slices.
