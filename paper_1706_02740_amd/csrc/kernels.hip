@@ -52,6 +52,13 @@ __device__ __forceinline__ void st2(GLOBAL float2* p, float2 v) {
     w.y = v.y;
     *(GLOBAL pod_f2*)p = w;
 }
+// a * b with both multiply-adds spelled out: every kernel that inlines it
+// rounds the same way (no contraction left to the compiler's choice), which
+// keeps the kernels that must agree bit for bit in agreement.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
+}
+
 typedef float pod_f4 __attribute__((ext_vector_type(4)));
 
 // Copies n float2 (n even, both ends 16-byte aligned) from global memory into
@@ -176,11 +183,6 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
 
 constexpr int kPhaseAnchor = 8;
 
-__device__ __forceinline__ float tap_weight(int32_t delta, int o, int P, float invP, float wnorm, float inv2sig2) {
-    const float v = (float)(delta - o * P) * invP;
-    return wnorm * expf(-v * v * inv2sig2);
-}
-
 __device__ __forceinline__ void store_bands(GLOBAL float2* __restrict__ S, int P, int b0, int nb, const float2* acc,
                                             float u, const CONSTANT float* rate, float step_rate) {
     float sn, cs;
@@ -194,10 +196,9 @@ __device__ __forceinline__ void store_bands(GLOBAL float2* __restrict__ S, int P
                 sincospif(2.0f * u * rate[b0 + bb], &sn, &cs);
                 ph = make_float2(cs, sn);
             } else {
-                ph = make_float2(ph.x * step.x - ph.y * step.y, ph.x * step.y + ph.y * step.x);
+                ph = cmul(ph, step);
             }
-            st2(S + (size_t)(b0 + bb) * P, make_float2(acc[bb].x * ph.x - acc[bb].y * ph.y,
-                                                        acc[bb].x * ph.y + acc[bb].y * ph.x));
+            st2(S + (size_t)(b0 + bb) * P, cmul(acc[bb], ph));
         }
     }
 }
@@ -220,14 +221,19 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
     const int s1 = d->s1;
     const int n1 = l & (s1 - 1);
     const int n2 = l >> d->log2s1;
-    const int n = (int)(((int64_t)n1 * p + (int64_t)n2 * s1) % P);
+    int n = n1 * p + n2 * s1;   // < 2 P
+    if (n >= P) n -= P;
     const int64_t N = d->N;
     const int64_t nN = (int64_t)n * N;
-    const int64_t jp = (2 * nN + P) / (2 * (int64_t)P);
+    // jp = floor((2 n N + P) / (2 P)): a double quotient, corrected to the exact floor
+    const int64_t num = 2 * nN + P, den = 2 * (int64_t)P;
+    int64_t jp = (int64_t)((double)num / (double)den);
+    const int64_t rem = num - jp * den;
+    if (rem < 0) --jp;
+    else if (rem >= den) ++jp;
     const int32_t delta = (int32_t)(nN - jp * P);
     const float Pf = (float)P;
     const float u = (float)delta / Pf;
-    const float invP = 1.0f / Pf;
     const int kappa = TAPS > 0 ? (TAPS - 1) / 2 : d->kappa;
     const int taps = TAPS > 0 ? TAPS : d->taps;
     const int Q = d->Q;
@@ -240,6 +246,8 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
     const bool interior = (jp - kappa >= 0) && (jp + kappa < N);
 
     if constexpr (TAPS > 0) {
+        static_assert(TAPS <= kFastTaps, "tap table");
+        constexpr int KP = (TAPS - 1) / 2;
         float2 x[TAPS];
 #pragma unroll
         for (int i = 0; i < TAPS; ++i) {
@@ -250,17 +258,35 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             }
             x[i] = ld2(f + idx);
         }
+        // W((delta - o P) / P) = wnorm exp(-(u - o)^2 c), o = i - kappa, c = inv2sig2,
+        //   = [wnorm exp(-u^2 c)] [exp(-o^2 c)] r^o,  r = exp(2 u c)
+        const float e0 = wnorm * expf(-u * u * inv2sig2);
+        const float r = expf(2.0f * u * inv2sig2);
+        const float ri = expf(-2.0f * u * inv2sig2);
+        float w[TAPS];
+        w[KP] = e0 * d->gtap[KP];
+        float rp = 1.0f, rn = 1.0f;
 #pragma unroll
-        for (int i = 0; i < TAPS; ++i) {
-            const float w = tap_weight(delta, i - kappa, P, invP, wnorm, inv2sig2);
-            x[i] = make_float2(x[i].x * w, x[i].y * w);
+        for (int o = 1; o <= KP; ++o) {
+            rp *= r;
+            rn *= ri;
+            w[KP + o] = e0 * d->gtap[KP + o] * rp;
+            w[KP - o] = e0 * d->gtap[KP - o] * rn;
         }
-        for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
-            const int nb = min(kBandChunk, Q - b0);
-            float2 acc[kBandChunk];
-            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * TAPS;
 #pragma unroll
-            for (int bb = 0; bb < kBandChunk; ++bb) {   // the table is zero-padded to whole chunks
+        for (int i = 0; i < TAPS; ++i) x[i] = make_float2(x[i].x * w[i], x[i].y * w[i]);
+        // two bands per pass (their 4 TAPS table values fit the scalar registers);
+        // band phasor exp(2 pi i u q_b / N): anchored every kPhaseAnchor bands,
+        // rotated by exp(2 pi i u 2L / N) in between
+        float sn, cs;
+        sincospif(2.0f * u * step_rate, &sn, &cs);
+        const float2 step = make_float2(cs, sn);
+        float2 ph = make_float2(1.f, 0.f);
+        for (int b0 = 0; b0 < Q; b0 += 2) {
+            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * TAPS;   // zero-padded past Q
+            float2 acc[2];
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
                 acc[bb] = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int i = 0; i < TAPS; ++i) {
@@ -269,9 +295,35 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                     acc[bb].y = fmaf(x[i].x, t.y, fmaf(x[i].y, t.x, acc[bb].y));
                 }
             }
-            store_bands(S, P, b0, nb, acc, u, rate, step_rate);
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+                const int b = b0 + bb;
+                if (b < Q) {
+                    if ((b % kPhaseAnchor) == 0) {
+                        sincospif(2.0f * u * rate[b], &sn, &cs);
+                        ph = make_float2(cs, sn);
+                    } else {
+                        ph = cmul(ph, step);
+                    }
+                    st2(S + (size_t)b * P, cmul(acc[bb], ph));
+                }
+            }
         }
     } else {
+        // the same weights as the compile-time kernels, bit for bit: r^|o| by
+        // |o| multiplications from 1 in the same order
+        const float e0 = wnorm * expf(-u * u * inv2sig2);
+        const float r = expf(2.0f * u * inv2sig2);
+        const float ri = expf(-2.0f * u * inv2sig2);
+        auto weight = [&](int i) {
+            const int o = i - kappa;
+            const float gt = taps <= kFastTaps ? d->gtap[i] : expf(-(float)(o * o) * inv2sig2);
+            if (o == 0) return e0 * gt;
+            const float rr = o > 0 ? r : ri;
+            float pw = 1.0f;
+            for (int k = 0; k < (o > 0 ? o : -o); ++k) pw *= rr;
+            return e0 * gt * pw;
+        };
         for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
             const int nb = min(kBandChunk, Q - b0);
             float2 acc[kBandChunk];
@@ -284,7 +336,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                     if (idx < 0) idx += N;
                     else if (idx >= N) idx -= N;
                 }
-                const float w = tap_weight(delta, i - kappa, P, invP, wnorm, inv2sig2);
+                const float w = weight(i);
                 const float2 fv = ld2(f + idx);
                 const float xr = fv.x * w;
                 const float xi = fv.y * w;
@@ -357,18 +409,18 @@ __device__ void fft_rows_lds(float2* buf, int rows, int s1, int lg, const float2
             const int b0 = (row << lg) + blk * (4 * h) + pos;
             float2 x0 = buf[b0], x1 = buf[b0 + h], x2 = buf[b0 + 2 * h], x3 = buf[b0 + 3 * h];
             const float2 w1 = tw[pos << (lg - ls)];
-            float2 y = make_float2(x1.x * w1.x - x1.y * w1.y, x1.x * w1.y + x1.y * w1.x);
+            float2 y = cmul(x1, w1);
             x1 = make_float2(x0.x - y.x, x0.y - y.y);
             x0 = make_float2(x0.x + y.x, x0.y + y.y);
-            y = make_float2(x3.x * w1.x - x3.y * w1.y, x3.x * w1.y + x3.y * w1.x);
+            y = cmul(x3, w1);
             x3 = make_float2(x2.x - y.x, x2.y - y.y);
             x2 = make_float2(x2.x + y.x, x2.y + y.y);
             const float2 w2 = tw[pos << (lg - ls - 1)];
             const float2 w3 = tw[(pos + h) << (lg - ls - 1)];
-            y = make_float2(x2.x * w2.x - x2.y * w2.y, x2.x * w2.y + x2.y * w2.x);
+            y = cmul(x2, w2);
             buf[b0 + 2 * h] = make_float2(x0.x - y.x, x0.y - y.y);
             buf[b0] = make_float2(x0.x + y.x, x0.y + y.y);
-            y = make_float2(x3.x * w3.x - x3.y * w3.y, x3.x * w3.y + x3.y * w3.x);
+            y = cmul(x3, w3);
             buf[b0 + 3 * h] = make_float2(x1.x - y.x, x1.y - y.y);
             buf[b0 + h] = make_float2(x1.x + y.x, x1.y + y.y);
         }
@@ -450,7 +502,7 @@ __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
             for (int k2 = 1; k2 < R2; ++k2) {
                 const float2 w = tw[n1 * k2];
                 const float2 b = z[it][k2];
-                z[it][k2] = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+                z[it][k2] = cmul(b, w);
             }
         }
     }

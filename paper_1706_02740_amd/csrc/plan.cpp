@@ -167,6 +167,10 @@ void fill_desc(const sft_plan_info& in, SigDesc* d) {
     d->accept_cap = ac;
     d->inv2sig2 = (float)(1.0 / (2.0 * in.sigma_t * in.sigma_t));
     d->wnorm = (float)(1.0 / (2.0 * M_PI * in.sigma_t));
+    for (int i = 0; i < kFastTaps; ++i) {
+        const double o = (double)(i - in.kappa);
+        d->gtap[i] = i < 2 * in.kappa + 1 ? (float)exp(-o * o / (2.0 * in.sigma_t * in.sigma_t)) : 0.f;
+    }
     d->a_first = (float)((double)in.q_first / (double)in.N);
     d->a_step = (float)(2.0 * (double)in.L / (double)in.N);
     d->c1sq_half = in.c1 * in.c1 / 2.0;

@@ -12,7 +12,8 @@ constexpr int kMaxK = SFT_MAX_MODULI;
 constexpr int kMaxG = 7;
 constexpr int kThreads = 256;          // workgroup size of every kernel but k_dft (4 wave64)
 constexpr int kDftThreads = 512;       // k_dft workgroup size (8 wave64)
-constexpr int kBandChunk = 16;         // bands accumulated per pass of the gather kernel
+constexpr int kBandChunk = 16;         // bands accumulated per pass of the generic gather kernel (table padding)
+constexpr int kFastTaps = 16;          // window widths with a compile-time gather kernel are at most this
 constexpr int kAcceptCap = 4096;       // bound on the accepted candidates per band kept in LDS
 constexpr int kMergeCap = 4096;        // band results merged per signal in LDS
 constexpr int kRowElems = 4096;        // complex values per workgroup in the split path's row FFTs
@@ -38,6 +39,7 @@ struct SigDesc {
     int32_t accept_cap;     // accepted candidates one band may hold: min(4096, pow2 >= 8 s)
     float   inv2sig2;       // 1 / (2 sigma_t^2)
     float   wnorm;          // 1 / (2 pi sigma_t): W(v) = wnorm exp(-v^2 inv2sig2)
+    float   gtap[kFastTaps];  // exp(-(i - kappa)^2 inv2sig2), i < taps (taps <= kFastTaps)
     float   a_first;        // q_first / N    (per-node band phase rate, in turns)
     float   a_step;         // 2 L / N
     double  c1sq_half;      // c1^2 / 2
