@@ -1091,9 +1091,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         const int mt = (h + 16) >> 4;
         const int ntw = s1 >> 6;
         pfa_mfma<MT, NTW>(bf, s1, p, h, mt, ntw, trig, Cm, Dm);
-        GLOBAL float* __restrict__ Ef = reinterpret_cast<GLOBAL float*>(E);
         const float sgn = plane ? -1.f : 1.f;
-        const uint32_t pofs = (uint32_t)p << (lg + 1);   // float offset of row p
 #pragma unroll
         for (int q = 0; q < NK; ++q) hi[q] = 0;
 #pragma unroll
@@ -1119,11 +1117,11 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
                     const float re = plane ? xm2 : xk;
                     const float im = plane ? xm : xk2;
                     hi[q] = __float_as_uint(fmaf(re, re, im * im));
-                    if (k <= h) {
-                        const uint32_t ok = ((uint32_t)k << (lg + 1)) + (uint32_t)N;
-                        Ef[ok] = xk;
-                        if (k >= 1) Ef[pofs - ((uint32_t)k << (lg + 1)) + (uint32_t)N] = xm;
-                        if (plane == 0 || k >= 1) valid |= (uint64_t)1 << q;
+                    // even lanes store X_k, odd lanes X_{p-k} (X_0 once, by the even lane)
+                    if (k <= h && (plane == 0 || k >= 1)) {
+                        const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
+                        st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));
+                        valid |= (uint64_t)1 << q;
                     }
                 }
             }
