@@ -16,6 +16,7 @@ times the FP64 oracle on a bounded sample of the same inputs on the host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n2e22_s64_batch256.txt")
+KERNELS_SRC = os.path.join(ROOT, "paper_1706_02740_amd", "csrc", "kernels.hip")
 
 METRIC = "SFTs/s + p50/p99 latency, batched vs plain, N=2^22 s=64, rel ℓ2 err≤1e-3"
 WORKLOAD = "plain_n2e22_s64_20db"
@@ -39,9 +42,9 @@ def kernel_work(info: dict) -> dict:
     k_gather : reads the 2 kappa + 1 window values of every node (8 B each) and
                writes Q complex64 samples per node; 8 (2 kappa + 1) flops per
                sample (a real-weighted tap times a band phasor, accumulated).
-    k_dft    : reads the Q M samples and writes the Q M bins (8 B each); flops
-               of the radix-2 row FFTs (5 P log2 s1 per DFT) and of the even/odd
-               p-point step (8 s1 h^2, h = (p - 1) / 2, per DFT).
+    k_dft,   : reads the Q M samples and writes the Q M bins (8 B each); flops
+    k_dft_mx   of the row FFTs (5 P log2 s1 per DFT) and of the even/odd p-point
+               step (8 s1 h^2, h = (p - 1) / 2, per DFT).
     Both sit below the FP32 ridge (about 9.8 flop/B without packed FP32), so
     their roofline is HBM bandwidth.
     """
@@ -51,7 +54,36 @@ def kernel_work(info: dict) -> dict:
     dft_bytes = 2 * Q * M * 8
     lg = int(math.log2(s1))
     dft_flops = Q * sum(5 * P * lg + 8 * s1 * ((p - 1) // 2) ** 2 for P, p in zip(info["P"], info["primes"]))
-    return {"k_gather": (gather_bytes, gather_flops), "k_dft": (dft_bytes, dft_flops)}
+    return {"k_gather": (gather_bytes, gather_flops), "k_dft": (dft_bytes, dft_flops),
+            "k_dft_mx": (dft_bytes, dft_flops)}
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, same batch), each
+    scaled by the ratio of a plain copy kernel's known bytes to what the same
+    counter read for it.  None when there is no summary or when kernels.hip
+    has changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    if vals.get("kernels_sha256") != sha:
+        return None
+    try:
+        copy_bytes = float(vals["copy_bytes"])
+        f_scale = copy_bytes / (float(vals["copy fetch_kib"]) * 1024.0)
+        w_scale = copy_bytes / (float(vals["copy write_kib"]) * 1024.0)
+        fetch = float(vals[f"{kernel} fetch_kib"]) * 1024.0 * f_scale
+        write = float(vals[f"{kernel} write_kib"]) * 1024.0 * w_scale
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "fetch_scale": f_scale, "write_scale": w_scale}
 
 
 def main():
@@ -166,8 +198,10 @@ def main():
     if dom in work and kern[dom]["avg_ms"] > 0:
         byts, flops = work[dom]
         ach = per_kernel[dom]["GBps"]
+        tr = measured_traffic(dom) if B == 256 else None
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None,
+                "traffic_detail": tr,
                 "algorithmic_bytes_per_launch": byts * B, "avg_launch_ms": kern[dom]["avg_ms"],
                 "transforms_per_launch": B}
     gb = per_kernel.get("k_gather", {}).get("GBps", 0.0)
@@ -211,12 +245,14 @@ def main():
                "rel_l2_vs_oracle_max": max(rels) if rels else None,
                "rel_l2_vs_truth_mean": float(np.mean(truth)) if truth else None}
 
-    if args.calib_copy_mib > 0:
+    if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
         n = args.calib_copy_mib * 2 ** 20 // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        flush = torch.ones(n, dtype=torch.float32, device="cuda")   # evicts src from the Infinity Cache
+        del flush
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
 
     out = {
