@@ -140,24 +140,34 @@ __device__ __forceinline__ int64_t pos_mod(int64_t x, int64_t m) {
     return r < 0 ? r + m : r;
 }
 
-// Exclusive scan of data[0..n) (LDS) in place; returns the total.  scratch: int32[256].
+// Exclusive scan of data[0..n) (LDS) in place for a kThreads workgroup;
+// returns the total.  Each thread scans a contiguous chunk; the chunk sums are
+// scanned by wave shuffles and one exchange of the wave totals.
+// scratch: int32[kThreads / 64].
 __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
     const int chunk = (n + kThreads - 1) / kThreads;
     const int beg = min(n, tid * chunk);
     const int end = min(n, beg + chunk);
     int sum = 0;
     for (int i = beg; i < end; ++i) sum += data[i];
-    scratch[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        const int v = tid >= off ? scratch[tid - off] : 0;
-        __syncthreads();
-        scratch[tid] += v;
-        __syncthreads();
+    int x = sum;   // inclusive scan within the wave
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    int run = tid > 0 ? scratch[tid - 1] : 0;
-    const int total = scratch[kThreads - 1];
+    if (lane == 63) scratch[wid] = x;
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        const int v = scratch[w];
+        base += w < wid ? v : 0;
+        total += v;
+    }
+    int run = base + x - sum;
     for (int i = beg; i < end; ++i) {
         const int v = data[i];
         data[i] = run;
@@ -1333,10 +1343,12 @@ __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
 // w = a (mod s1), w = h_g (mod p_g) by the CRT in int64, mapped into B.
 // Vote ("more than half", Appendix B): the tuple's own G moduli hold heavy bins
 // at w by construction, so (w mod P_j) must be a heavy bin for more than half of
-// the other K - G moduli; a bin is heavy when its key is at least the block's
-// threshold, the key computed from the same E value as in the selection.  A w produced by both tuples is accepted if either
-// tuple's vote passes (the two entries are equal and merged later).  Estimate:
-// componentwise median of E_b[j][w mod P_j] over all K moduli.  Then the s
+// the other K - G moduli; a bin is heavy when it is in its block's heavy set
+// (key >= threshold), tested against an LDS bitmap built from the heavy bins,
+// so that E is read only for accepted candidates.  A w produced by both tuples
+// is accepted if either tuple's vote passes (the two entries are equal and
+// merged later).  Estimate: componentwise median of E_b[j][w mod P_j] over all
+// K moduli.  Then the s
 // largest |z| (ties to the smaller w), the band test w in [q_b - L, q_b + L),
 // and v = z / ghat_{w - q_b} in FP64.
 
@@ -1378,24 +1390,66 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     int32_t* flag = reinterpret_cast<int32_t*>(smem + (size_t)acap * 16);
     int32_t* scratch = flag + acap;
     int32_t* pre = scratch + kThreads;
-    uint64_t* thr = reinterpret_cast<uint64_t*>(pre + ((nslots + 2) & ~1));   // [K]
-    uint8_t* ccount = reinterpret_cast<uint8_t*>(thr + kMaxK);                // [K * s1]
+    uint8_t* ccount = reinterpret_cast<uint8_t*>(pre + ((nslots + 2) & ~1));   // [K * s1]
+    // heavy-bin bitmaps of the band's K blocks: bit h of block jj at word woff[jj] + h / 32
+    uint32_t* bm = reinterpret_cast<uint32_t*>(ccount + (((size_t)K * s1 + 3) & ~(size_t)3));
+    int woff[kMaxK + 1];
+    woff[0] = 0;
+#pragma unroll
+    for (int jj = 0; jj < kMaxK; ++jj) woff[jj + 1] = woff[jj] + (jj < K ? (d->P[jj] + 31) >> 5 : 0);
     __shared__ int32_t sh_cnt;
 
     const GLOBAL int32_t* __restrict__ CLall = glb(io.CL);
     const GLOBAL float2* __restrict__ Eall = glb(io.E);
     const size_t cl_stride = (size_t)s1 * depth;   // one (modulus, band) block of class lists
 
-    // 0. thresholds and class-list lengths of this band's K blocks, into LDS
-    for (int jj = tid; jj < K; jj += kThreads) thr[jj] = glb(io.thr)[jj * Q + b];
-    for (int i = tid; i < K * s1; i += kThreads) {
-        const int jj = i >> lg;
-        const int ac = i & (s1 - 1);
-        const GLOBAL int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
-        int n = 0;
+    // 0. class-list lengths and heavy-bin bitmaps of this band's K blocks, into LDS
+    for (int i = tid; i < woff[kMaxK]; i += kThreads) bm[i] = 0;
+    __syncthreads();   // bitmaps cleared
+    {
+        // class-list lengths (lists are -1 padded) and the heavy bins of block
+        // (jj, b) (its min(T, P_jj) entries of H, unordered); a thread's loads of
+        // a round are all issued before their first use
+        constexpr int U = 4;
+        const int T = d->T;
+        const GLOBAL int32_t* __restrict__ Hall = glb(io.H);
+        for (int i0 = tid; i0 < K * s1 || i0 < K * T; i0 += U * kThreads) {
+            int32_t hv[U];
+            int32_t lv[U][kMaxDepth];
 #pragma unroll
-        for (int e = 0; e < kMaxDepth; ++e) n += (e < depth && cl[e] >= 0) ? 1 : 0;   // lists are -1 padded
-        ccount[i] = (uint8_t)n;
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * kThreads;
+                hv[u] = -1;
+                if (i < K * T) {
+                    const int jj = i / T;
+                    const int e = i - jj * T;
+                    if (e < d->P[jj]) hv[u] = Hall[(size_t)(jj * Q + b) * T + e];
+                }
+#pragma unroll
+                for (int e = 0; e < kMaxDepth; ++e) lv[u][e] = -1;
+                if (i < K * s1) {
+                    const GLOBAL int32_t* cl =
+                        CLall + (size_t)((i >> lg) * Q + b) * cl_stride + (size_t)(i & (s1 - 1)) * depth;
+#pragma unroll
+                    for (int e = 0; e < kMaxDepth; ++e)
+                        if (e < depth) lv[u][e] = cl[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * kThreads;
+                if (hv[u] >= 0) {
+                    const int jj = i / T;
+                    atomicOr(&bm[woff[jj] + (hv[u] >> 5)], 1u << (hv[u] & 31));
+                }
+                if (i < K * s1) {
+                    int n = 0;
+#pragma unroll
+                    for (int e = 0; e < kMaxDepth; ++e) n += lv[u][e] >= 0 ? 1 : 0;
+                    ccount[i] = (uint8_t)n;
+                }
+            }
+        }
     }
     __syncthreads();
 
@@ -1414,6 +1468,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     __syncthreads();
 
     // 2. candidates -> vote -> median
+    const bool small_n = d->N <= ((int64_t)1 << 31);   // then B lies in the int32 range
     for (int c = tid; c < total; c += kThreads) {
         int l0 = 0, h0 = nslots - 1;   // last slot with pre[slot] <= c
         while (l0 < h0) {
@@ -1424,44 +1479,67 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         int r = c - pre[slot];
         const int t = slot >> lg;
         const int ac = slot & (s1 - 1);
-        int64_t x = (int64_t)((ac * (int64_t)d->tup_inv[t][0]) % s1) * d->tup_Mi[t][0];
-        for (int g = 0; g < G; ++g) {
-            const int jj = d->tup_j[t][g];
-            const GLOBAL int32_t* cl = CLall + (size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth;
-            const int cg = ccount[(jj << lg) + ac];
-            const int ch = r % cg;
-            r /= cg;
-            const int32_t h = cl[ch];
-            const int pm = d->tup_mod[t][g + 1];
-            const int64_t res = h % pm;
-            x += ((res * d->tup_inv[t][g + 1]) % pm) * d->tup_Mi[t][g + 1];
+        // CRT without 64-bit divisions: every term is below M_t (a residue < m
+        // times M_t / m), so the sum is reduced by at most G subtractions
+        int64_t x = (int64_t)((ac * d->tup_inv[t][0]) & (s1 - 1)) * d->tup_Mi[t][0];
+        int32_t hg[kMaxG];   // the combination's bin of every modulus of the tuple (loads issued together)
+#pragma unroll
+        for (int g = 0; g < kMaxG; ++g) {
+            if (g < G) {
+                const int jj = d->tup_j[t][g];
+                const int cg = ccount[(jj << lg) + ac];
+                const int ch = r % cg;
+                r /= cg;
+                hg[g] = CLall[(size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth + ch];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kMaxG; ++g) {
+            if (g < G) {
+                const uint32_t pm = (uint32_t)d->tup_mod[t][g + 1];
+                const uint32_t res = (uint32_t)hg[g] % pm;
+                x += (int64_t)((res * (uint32_t)d->tup_inv[t][g + 1]) % pm) * d->tup_Mi[t][g + 1];
+            }
         }
         const int64_t Mt = d->tup_M[t];
-        x %= Mt;
+        while (x >= Mt) x -= Mt;
         int64_t w;
         if (x <= hi) w = x;
         else if (x - Mt >= lo) w = x - Mt;
         else continue;
 
-        // the bins of w in every modulus: values for the median, keys for the vote
-        float er[kMaxK], ei[kMaxK];
-        int votes = 0;                 // heavy bins among the moduli outside tuple t
+        // the bin of w in every modulus; the vote counts heavy bins among the
+        // moduli outside tuple t (a bin is heavy iff its key >= the block's
+        // threshold, i.e. iff it is in the block's heavy set)
+        int hh[kMaxK];
+        int votes = 0;
         const int t_lo = t * G, t_hi = t_lo + G;
 #pragma unroll
         for (int jj = 0; jj < kMaxK; ++jj) {
             if (jj < K) {
-                const int Pj = d->P[jj];
-                const int hh = (int)pos_mod(w, Pj);
-                const int cls = hh & (s1 - 1);
-                const int k2 = hh % d->p[jj];
-                const float2 ev = ld2(Eall + (size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) + cls);
-                const bool heavy = value_key(ev, (uint32_t)hh) >= thr[jj];
+                if (small_n) {   // w fits 32 bits
+                    const int r32 = (int)w % d->P[jj];
+                    hh[jj] = r32 < 0 ? r32 + d->P[jj] : r32;
+                } else {
+                    hh[jj] = (int)pos_mod(w, d->P[jj]);
+                }
+                const bool heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
                 votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
-                er[jj] = ev.x;
-                ei[jj] = ev.y;
             }
         }
         if (2 * votes > K - G) {
+            float er[kMaxK], ei[kMaxK];   // the K bin values, for the median
+#pragma unroll
+            for (int jj = 0; jj < kMaxK; ++jj) {
+                if (jj < K) {
+                    const int Pj = d->P[jj];
+                    const int k2 = hh[jj] % d->p[jj];
+                    const float2 ev = ld2(Eall + (size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) +
+                                          (hh[jj] & (s1 - 1)));
+                    er[jj] = ev.x;
+                    ei[jj] = ev.y;
+                }
+            }
             const float zr = median_of(er, K);
             const float zi = median_of(ei, K);
             const float m2 = fmaf(zr, zr, zi * zi);
@@ -1477,31 +1555,64 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     }
     __syncthreads();
     const int nacc = min(sh_cnt, acap);
-    int np2 = 1;
-    while (np2 < nacc) np2 <<= 1;
-    for (int i = nacc + tid; i < np2; i += kThreads) {
-        akey[i] = 0;
-        az[i] = make_float2(0.f, 0.f);
-    }
-    __syncthreads();
     // 3. sort accepted by key descending (|z|^2 desc, w asc)
-    for (int kk = 2; kk <= np2; kk <<= 1) {
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < np2; i += kThreads) {
-                const int ixj = i ^ jj;
-                if (ixj > i) {
-                    const bool desc = (i & kk) == 0;
-                    const uint64_t ki = akey[i], kx = akey[ixj];
-                    if (desc ? (kx > ki) : (kx < ki)) {
-                        akey[i] = kx;
-                        akey[ixj] = ki;
-                        const float2 zt = az[i];
-                        az[i] = az[ixj];
-                        az[ixj] = zt;
+    if (nacc <= 2 * kThreads) {
+        // by rank: an entry's position is the number of entries ahead of it
+        // (a larger key, or an equal key at a lower index)
+        uint64_t kk[2];
+        float2 zz[2];
+        int rk[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = tid + u * kThreads;
+            rk[u] = -1;
+            if (i < nacc) {
+                const uint64_t k = akey[i];
+                int r = 0;
+                for (int jn = 0; jn < nacc; ++jn) {
+                    const uint64_t kj = akey[jn];
+                    r += (kj > k || (kj == k && jn < i)) ? 1 : 0;
+                }
+                kk[u] = k;
+                zz[u] = az[i];
+                rk[u] = r;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (rk[u] >= 0) {
+                akey[rk[u]] = kk[u];
+                az[rk[u]] = zz[u];
+            }
+        }
+        __syncthreads();
+    } else {   // bitonic sort of the entries padded with zero keys to a power of two
+        int np2 = 1;
+        while (np2 < nacc) np2 <<= 1;
+        for (int i = nacc + tid; i < np2; i += kThreads) {
+            akey[i] = 0;
+            az[i] = make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        for (int kk = 2; kk <= np2; kk <<= 1) {
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int i = tid; i < np2; i += kThreads) {
+                    const int ixj = i ^ jj;
+                    if (ixj > i) {
+                        const bool desc = (i & kk) == 0;
+                        const uint64_t ki = akey[i], kx = akey[ixj];
+                        if (desc ? (kx > ki) : (kx < ki)) {
+                            akey[i] = kx;
+                            akey[ixj] = ki;
+                            const float2 zt = az[i];
+                            az[i] = az[ixj];
+                            az[ixj] = zt;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     // 4. distinct entries, the first s of them (R_temp), then the band test
@@ -1631,8 +1742,10 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
 
 size_t identify_lds_bytes(const SigDesc& d) {
     const int nslots = 2 * d.s1;
-    return (size_t)d.accept_cap * 20 + (size_t)kThreads * 4 + (size_t)((nslots + 2) & ~1) * 4 + kMaxK * 8 +
-           (size_t)d.K * d.s1 + 64;
+    size_t words = 0;   // heavy-bin bitmaps
+    for (int j = 0; j < d.K; ++j) words += (size_t)(d.P[j] + 31) / 32;
+    return (size_t)d.accept_cap * 20 + (size_t)kThreads * 4 + (size_t)((nslots + 2) & ~1) * 4 +
+           (((size_t)d.K * d.s1 + 3) & ~(size_t)3) + words * 4 + 64;
 }
 
 size_t merge_lds_bytes() {
