@@ -86,6 +86,42 @@ def measured_traffic(kernel: str):
             "fetch_scale": f_scale, "write_scale": w_scale}
 
 
+def uneven_batch(sft, siggen, torch, stream, reps: int = 3) -> dict:
+    """The uneven batch: 256 signals (N from 2^18..2^24, 3*2^20, 5*2^19+1; s in
+    [16, 256]; 30 dB; batch seed 0) in one sft_execute_many, against the same
+    256 transforms as plain sft_execute calls; outputs compared bit for bit."""
+    shapes = siggen.batched_shapes(0)
+    plans, pl, fs = {}, [], []
+    for N, s, seed in shapes:
+        if (N, s) not in plans:
+            plans[(N, s)] = sft.Plan(N, s)
+        pl.append(plans[(N, s)])
+        fs.append(siggen.sparse_signal_device(N, s, seed, 30.0)[0])
+    outs = [(torch.empty(p.s, dtype=torch.int64, device="cuda"), torch.empty(p.s, dtype=torch.complex64, device="cuda"))
+            for p in pl]
+    counts = torch.empty(len(pl), dtype=torch.int32, device="cuda")
+    sft.execute_many(pl, fs, outs, counts, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sft.execute_many(pl, fs, outs, counts, stream)
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / reps
+    pouts = [p.outputs() for p in pl]
+    t0 = time.perf_counter()
+    for p, f, o in zip(pl, fs, pouts):
+        p.execute(f, o)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    equal = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(outs, pouts))
+    samples = sum(p.info["Q"] * p.info["M"] for p in pl)
+    print(f"[bench] uneven batch: {batched_s * 1e3:.2f} ms batched, {plain_s * 1e3:.2f} ms as plain calls", file=sys.stderr,
+          flush=True)
+    return {"signals": len(pl), "plans": len(plans), "batched_sft_per_s": len(pl) / batched_s,
+            "plain_sft_per_s": len(pl) / plain_s, "batch_ms": batched_s * 1e3, "plain_ms": plain_s * 1e3,
+            "filtered_samples": samples, "outputs_equal": bool(equal)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +133,7 @@ def main():
     ap.add_argument("--latency-calls", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -245,6 +282,8 @@ def main():
                "rel_l2_vs_oracle_max": max(rels) if rels else None,
                "rel_l2_vs_truth_mean": float(np.mean(truth)) if truth else None}
 
+    uneven = None if args.no_uneven else uneven_batch(sft, siggen, torch, stream)
+
     if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
         n = args.calib_copy_mib * 2 ** 20 // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -273,6 +312,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy": acc,
+        "uneven_batch": uneven,
     }
     print(json.dumps(out), flush=True)
 

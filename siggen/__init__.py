@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "band_limits", "SparseSignal", "draw_frequencies", "draw_coefficients",
     "synthesize", "add_noise", "sparse_signal", "workload",
-    "WORKLOADS", "batched_shapes", "serving_requests",
+    "WORKLOADS", "batched_shapes", "serving_requests", "sparse_signal_device",
 ]
 
 
@@ -91,6 +91,31 @@ def sparse_signal(N: int, s: int, seed: int, snr_db: Optional[float] = None,
     f_clean = synthesize(N, freqs, coefs)
     f = f_clean if snr_db is None else add_noise(f_clean, snr_db, rng)
     return SparseSignal(N, s, freqs, coefs, snr_db, f, f_clean)
+
+
+def sparse_signal_device(N: int, s: int, seed: int, snr_db: Optional[float] = None,
+                         magnitude: str = "unit", device: str = "cuda"):
+    """The generator of sparse_signal with the synthesis and the noise on a
+    torch device (for large batches): the same frequencies and coefficients
+    (numpy PCG64(seed)), f = N ifft(c) in complex128 on the device, noise from
+    torch's generator seeded with `seed` (so it differs from sparse_signal's
+    noise), rescaled to the exact SNR.  Returns (f complex64 tensor, freqs, coefs)."""
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    freqs = draw_frequencies(N, s, rng)
+    coefs = draw_coefficients(s, rng, magnitude)
+    spec = torch.zeros(N, dtype=torch.complex128, device=device)
+    spec.index_put_((torch.from_numpy(np.mod(freqs, N)).to(device),),
+                    torch.from_numpy(coefs).to(device), accumulate=True)
+    f = torch.fft.ifft(spec) * N
+    if snr_db is not None:
+        g = torch.Generator(device=device)
+        g.manual_seed(seed)
+        n = torch.complex(torch.randn(N, dtype=torch.float64, device=device, generator=g),
+                          torch.randn(N, dtype=torch.float64, device=device, generator=g))
+        f = f + n * (torch.linalg.vector_norm(f) / (torch.linalg.vector_norm(n) * 10.0 ** (snr_db / 20.0)))
+    return f.to(torch.complex64), freqs, coefs
 
 
 # The five workloads.  Keys name what they are.

@@ -197,6 +197,38 @@ def test_batched_equals_plain_mixed_plans(gpu):
     gpu.execute_many([], [])
 
 
+def test_config4_uneven_batch_equals_plain(gpu):
+    """The uneven batch: 256 signals, N drawn from 2^18..2^24, 3*2^20 and
+    5*2^19+1, s from [16, 256], 30 dB, in one execute_many (every DFT path
+    occurs: matrix-core, VALU and split) equal the 256 single calls bit for
+    bit; the smallest signals also match the oracle."""
+    shapes = siggen.batched_shapes(0)
+    plans, pl, fs = {}, [], []
+    for N, s, seed in shapes:
+        if (N, s) not in plans:
+            plans[(N, s)] = gpu.Plan(N, s)
+        pl.append(plans[(N, s)])
+        fs.append(siggen.sparse_signal_device(N, s, seed, 30.0)[0])
+    torch.cuda.synchronize()
+    say("uneven batch", len(shapes), "signals,", len(plans), "plans")
+    outs, counts = gpu.execute_many(pl, fs)
+    torch.cuda.synchronize()
+    for i, (p, f) in enumerate(zip(pl, fs)):
+        w, c, n = p.execute(f)
+        torch.cuda.synchronize()
+        k = int(n.item())
+        assert int(counts[i].item()) == k, i
+        assert np.array_equal(outs[i][0].cpu().numpy(), w.cpu().numpy()), i
+        assert np.array_equal(outs[i][1].cpu().numpy(), c.cpu().numpy()), i
+    for i in sorted(range(len(shapes)), key=lambda i: shapes[i][0])[:3]:
+        N, s, _ = shapes[i]
+        say("uneven batch vs oracle", i, N, s)
+        k = int(counts[i].item())
+        wg, cg = outs[i][0].cpu().numpy()[:k], outs[i][1].cpu().numpy()[:k]
+        wo, co = oracle.sft(oracle.make_plan(N, s), fs[i].cpu().numpy())
+        assert_same_result(wg, cg, wo, co)
+
+
 @pytest.mark.parametrize("N,s,snr,kw", [(2 ** 14, 8, 30.0, {}), (100_003, 20, 20.0, {}),
                                         (2 ** 16, 100, 10.0, {"preset": 1}), (2 ** 14, 8, None, {"preset": 2})])
 def test_split_dft_path_equals_in_lds_path(gpu, N, s, snr, kw):
