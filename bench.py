@@ -122,6 +122,51 @@ def uneven_batch(sft, siggen, torch, stream, reps: int = 3) -> dict:
             "filtered_samples": samples, "outputs_equal": bool(equal)}
 
 
+def serving_runs(sft, siggen, torch, distinct: int = 256, arrivals: int = 1024,
+                 loads=(0.5, 0.8, 0.95)) -> dict:
+    """The serving mix: requests with N uniform over 2^20..2^26, s log-uniform
+    in [16, 1024], SNR uniform in [0, 40] dB (serving generator, seed 0).
+    `distinct` inputs are generated and kept resident; the arrival stream
+    replays them in order.  Capacity = the requests of one saturated run (all
+    arriving at once) per second; then Poisson arrivals at each offered load
+    (a fraction of that capacity), with p50/p99 arrival-to-result latency."""
+    from paper_1706_02740_amd import serve
+    spec = siggen.serving_requests(0, distinct, rate_hz=1.0)
+    plans, inputs = {}, []
+    for rq in spec:
+        key = (rq["N"], rq["s"])
+        if key not in plans:
+            plans[key] = sft.Plan(*key)
+        inputs.append((plans[key], siggen.sparse_signal_device(rq["N"], rq["s"], rq["seed"], rq["snr_db"])[0]))
+    torch.cuda.synchronize()
+    budget = 24 << 30
+
+    def trace(arrival_times):
+        reqs = [serve.Request(rid=i, plan=inputs[i % distinct][0], f=inputs[i % distinct][1], arrival=t,
+                              nbytes=serve.footprint_bytes(inputs[i % distinct][0]))
+                for i, t in enumerate(arrival_times)]
+        srv = serve.Server(serve.GpuExecutor(slots=2), budget_bytes=budget, max_batch=256)
+        t0 = time.perf_counter()
+        serve.run_trace(srv, reqs)
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t0
+        lat = np.array([r.latency for r in srv.completed]) * 1e3
+        return {"requests": len(srv.completed), "sft_per_s": len(srv.completed) / span, "batches": srv.batches,
+                "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}
+
+    trace([0.0] * distinct)   # warm-up: arenas and kernels
+    sat = trace([0.0] * distinct)
+    cap = sat["sft_per_s"]
+    out = {"distinct_inputs": distinct, "plans": len(plans), "saturated": sat, "offered": {}}
+    rng = np.random.Generator(np.random.PCG64(7))
+    for rho in loads:
+        t = np.cumsum(rng.exponential(1.0 / (rho * cap), size=arrivals))
+        out["offered"][str(rho)] = trace(list(t))
+        print(f"[bench] serving at {rho:.2f} x capacity: p50 {out['offered'][str(rho)]['latency_ms_p50']:.2f} ms, "
+              f"p99 {out['offered'][str(rho)]['latency_ms_p99']:.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +179,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -283,6 +329,7 @@ def main():
                "rel_l2_vs_truth_mean": float(np.mean(truth)) if truth else None}
 
     uneven = None if args.no_uneven else uneven_batch(sft, siggen, torch, stream)
+    serving = None if args.no_serve else serving_runs(sft, siggen, torch)
 
     if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
         n = args.calib_copy_mib * 2 ** 20 // 4
@@ -313,6 +360,7 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": acc,
         "uneven_batch": uneven,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -1391,13 +1391,16 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     int32_t* scratch = flag + acap;
     int32_t* pre = scratch + kThreads;
     uint8_t* ccount = reinterpret_cast<uint8_t*>(pre + ((nslots + 2) & ~1));   // [K * s1]
-    // heavy-bin bitmaps of the band's K blocks: bit h of block jj at word woff[jj] + h / 32
+    // heavy-bin bitmaps of the band's K blocks (when they fit the LDS): bit h of
+    // block jj at word woff[jj] + h / 32; otherwise the vote compares keys
+    const bool use_bm = d->vote_bitmap != 0;
     uint32_t* bm = reinterpret_cast<uint32_t*>(ccount + (((size_t)K * s1 + 3) & ~(size_t)3));
     int woff[kMaxK + 1];
     woff[0] = 0;
 #pragma unroll
-    for (int jj = 0; jj < kMaxK; ++jj) woff[jj + 1] = woff[jj] + (jj < K ? (d->P[jj] + 31) >> 5 : 0);
+    for (int jj = 0; jj < kMaxK; ++jj) woff[jj + 1] = woff[jj] + (jj < K && use_bm ? (d->P[jj] + 31) >> 5 : 0);
     __shared__ int32_t sh_cnt;
+    __shared__ uint64_t sh_thr[kMaxK];   // the blocks' thresholds (key vote)
 
     const GLOBAL int32_t* __restrict__ CLall = glb(io.CL);
     const GLOBAL float2* __restrict__ Eall = glb(io.E);
@@ -1405,6 +1408,8 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
 
     // 0. class-list lengths and heavy-bin bitmaps of this band's K blocks, into LDS
     for (int i = tid; i < woff[kMaxK]; i += kThreads) bm[i] = 0;
+    if (!use_bm)
+        for (int jj = tid; jj < K; jj += kThreads) sh_thr[jj] = glb(io.thr)[jj * Q + b];
     __syncthreads();   // bitmaps cleared
     {
         // class-list lengths (lists are -1 padded) and the heavy bins of block
@@ -1413,14 +1418,15 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         constexpr int U = 4;
         const int T = d->T;
         const GLOBAL int32_t* __restrict__ Hall = glb(io.H);
-        for (int i0 = tid; i0 < K * s1 || i0 < K * T; i0 += U * kThreads) {
+        const int nh = use_bm ? K * T : 0;
+        for (int i0 = tid; i0 < K * s1 || i0 < nh; i0 += U * kThreads) {
             int32_t hv[U];
             int32_t lv[U][kMaxDepth];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int i = i0 + u * kThreads;
                 hv[u] = -1;
-                if (i < K * T) {
+                if (i < nh) {
                     const int jj = i / T;
                     const int e = i - jj * T;
                     if (e < d->P[jj]) hv[u] = Hall[(size_t)(jj * Q + b) * T + e];
@@ -1514,21 +1520,8 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         int hh[kMaxK];
         int votes = 0;
         const int t_lo = t * G, t_hi = t_lo + G;
-#pragma unroll
-        for (int jj = 0; jj < kMaxK; ++jj) {
-            if (jj < K) {
-                if (small_n) {   // w fits 32 bits
-                    const int r32 = (int)w % d->P[jj];
-                    hh[jj] = r32 < 0 ? r32 + d->P[jj] : r32;
-                } else {
-                    hh[jj] = (int)pos_mod(w, d->P[jj]);
-                }
-                const bool heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
-                votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
-            }
-        }
-        if (2 * votes > K - G) {
-            float er[kMaxK], ei[kMaxK];   // the K bin values, for the median
+        float er[kMaxK], ei[kMaxK];   // the K bin values, for the median
+        auto read_bins = [&]() {
 #pragma unroll
             for (int jj = 0; jj < kMaxK; ++jj) {
                 if (jj < K) {
@@ -1540,6 +1533,38 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                     ei[jj] = ev.y;
                 }
             }
+        };
+#pragma unroll
+        for (int jj = 0; jj < kMaxK; ++jj) {
+            if (jj < K) {
+                if (small_n) {   // w fits 32 bits
+                    const int r32 = (int)w % d->P[jj];
+                    hh[jj] = r32 < 0 ? r32 + d->P[jj] : r32;
+                } else {
+                    hh[jj] = (int)pos_mod(w, d->P[jj]);
+                }
+            }
+        }
+        if (use_bm) {
+#pragma unroll
+            for (int jj = 0; jj < kMaxK; ++jj) {
+                if (jj < K) {
+                    const bool heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
+                    votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
+                }
+            }
+        } else {   // the same heavy test from the bin values: key >= the block's threshold
+            read_bins();
+#pragma unroll
+            for (int jj = 0; jj < kMaxK; ++jj) {
+                if (jj < K) {
+                    const bool heavy = value_key(make_float2(er[jj], ei[jj]), (uint32_t)hh[jj]) >= sh_thr[jj];
+                    votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
+                }
+            }
+        }
+        if (2 * votes > K - G) {
+            if (use_bm) read_bins();
             const float zr = median_of(er, K);
             const float zi = median_of(ei, K);
             const float m2 = fmaf(zr, zr, zi * zi);
@@ -1740,10 +1765,11 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
 
 // ------------------------------------------------------------ launchers ---
 
-size_t identify_lds_bytes(const SigDesc& d) {
+size_t identify_lds_bytes(const SigDesc& d, bool bitmap) {
     const int nslots = 2 * d.s1;
     size_t words = 0;   // heavy-bin bitmaps
-    for (int j = 0; j < d.K; ++j) words += (size_t)(d.P[j] + 31) / 32;
+    if (bitmap)
+        for (int j = 0; j < d.K; ++j) words += (size_t)(d.P[j] + 31) / 32;
     return (size_t)d.accept_cap * 20 + (size_t)kThreads * 4 + (size_t)((nslots + 2) & ~1) * 4 +
            (((size_t)d.K * d.s1 + 3) & ~(size_t)3) + words * 4 + 64;
 }

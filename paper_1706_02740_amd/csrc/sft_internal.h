@@ -37,6 +37,7 @@ struct SigDesc {
     int64_t lo, hi;         // B = [lo, hi]
     int32_t s, kappa, taps, Q, K, G, s1, log2s1, T, depth, M, Tpow2;
     int32_t accept_cap;     // accepted candidates one band may hold: min(4096, pow2 >= 8 s)
+    int32_t vote_bitmap;    // 1: identify votes from LDS heavy-bin bitmaps (they fit); 0: from bin keys
     float   inv2sig2;       // 1 / (2 sigma_t^2)
     float   wnorm;          // 1 / (2 pi sigma_t): W(v) = wnorm exp(-v^2 inv2sig2)
     float   gtap[kFastTaps];  // exp(-(i - kappa)^2 inv2sig2), i < taps (taps <= kFastTaps)
@@ -137,7 +138,7 @@ hipError_t launch_dft_cols(const BatchArgs& a, int blocks, size_t lds, hipStream
 hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_merge(const BatchArgs& a, int blocks, hipStream_t st);
 hipError_t configure_kernels(int max_lds);
-size_t identify_lds_bytes(const SigDesc& d);
+size_t identify_lds_bytes(const SigDesc& d, bool bitmap);   // with or without the heavy-bin bitmaps
 size_t merge_lds_bytes();
 
 }  // namespace sft

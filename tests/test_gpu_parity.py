@@ -229,6 +229,38 @@ def test_config4_uneven_batch_equals_plain(gpu):
         assert_same_result(wg, cg, wo, co)
 
 
+def test_serving_mix_results_equal_alone(gpu):
+    """The serving loop: requests of uneven N (2^20..2^23) and s (16..1024,
+    log-uniform), 0-40 dB, arriving faster than the device completes them, are
+    batched continuously on two streams; every result equals the same request
+    run alone, bit for bit; a request above the memory budget is rejected and
+    the others are unaffected."""
+    from paper_1706_02740_amd import serve
+    plans, reqs = {}, []
+    for i, rq in enumerate(siggen.serving_requests(0, 64, rate_hz=20_000.0, min_log2=20, max_log2=23)):
+        key = (rq["N"], rq["s"])
+        if key not in plans:
+            plans[key] = gpu.Plan(*key)
+        p = plans[key]
+        f = siggen.sparse_signal_device(rq["N"], rq["s"], rq["seed"], rq["snr_db"])[0]
+        reqs.append(serve.Request(rid=i, plan=p, f=f, arrival=rq["t"], nbytes=serve.footprint_bytes(p)))
+    budget = 3 << 30
+    reqs[5].nbytes = budget + 1
+    torch.cuda.synchronize()
+    say("serving", len(reqs), "requests,", len(plans), "plans")
+    srv = serve.Server(serve.GpuExecutor(slots=2), budget_bytes=budget, max_batch=16)
+    serve.run_trace(srv, reqs)
+    torch.cuda.synchronize()
+    assert [r.rid for r in srv.rejected] == [5]
+    assert len(srv.completed) == len(reqs) - 1
+    assert srv.max_inflight == 2 and srv.batches >= 4 and srv.max_held <= budget
+    for r in srv.completed:
+        w, c, n = r.plan.execute(r.f)
+        torch.cuda.synchronize()
+        assert int(r.result[2].item()) == int(n.item()), r.rid
+        assert torch.equal(r.result[0], w) and torch.equal(r.result[1], c), r.rid
+
+
 @pytest.mark.parametrize("N,s,snr,kw", [(2 ** 14, 8, 30.0, {}), (100_003, 20, 20.0, {}),
                                         (2 ** 16, 100, 10.0, {"preset": 1}), (2 ** 14, 8, None, {"preset": 2})])
 def test_split_dft_path_equals_in_lds_path(gpu, N, s, snr, kw):
