@@ -167,6 +167,37 @@ def serving_runs(sft, siggen, torch, distinct: int = 256, arrivals: int = 1024,
     return out
 
 
+def noise_robustness(sft, siggen, torch, stream, trials: int = 100,
+                     snrs=(-20, -10, 0, 10, 20, 30, 40, 50, 60)) -> dict:
+    """Section 5.4's protocol for this method: N = 2^22, s = 50, unit-magnitude
+    random-phase coefficients, complex Gaussian noise at each SNR (dB), 100
+    trial signals per level.  Reports the fraction of trials whose recovered
+    support is the true one and, over those, the mean of the average L1 error
+    (1/s) sum_{w in S} |c_w - z_w|."""
+    N, s = 2 ** 22, 50
+    plan = sft.Plan(N, s)
+    out = {}
+    for snr in snrs:
+        fs, truth = [], []
+        for t in range(trials):
+            f, fr, co = siggen.sparse_signal_device(N, s, 5_000_000 + 1000 * snr + t, float(snr))
+            fs.append(f)
+            truth.append(dict(zip(fr.tolist(), co)))
+        res, counts = sft.execute_many([plan] * trials, fs, stream=stream)
+        torch.cuda.synchronize()
+        ok, errs = 0, []
+        for (w, c), n, tr in zip(res, counts.cpu().numpy(), truth):
+            wg, cg = w.cpu().numpy()[:n], c.cpu().numpy()[:n]
+            if set(wg.tolist()) == set(tr):
+                ok += 1
+                errs.append(sum(abs(complex(cv) - tr[int(wv)]) for wv, cv in zip(wg, cg)) / s)
+        out[str(snr)] = {"support_rate": ok / trials, "avg_l1_error": float(np.mean(errs)) if errs else None}
+        del fs
+    print("[bench] noise robustness: " + ", ".join(f"{k} dB: {v['support_rate']:.2f} / {v['avg_l1_error']}"
+                                                 for k, v in out.items()), file=sys.stderr, flush=True)
+    return {"N": N, "s": s, "trials": trials, "by_snr_db": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +211,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop runs")
+    ap.add_argument("--no-noise", action="store_true", help="skip the noise-robustness sweep")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -330,6 +362,7 @@ def main():
 
     uneven = None if args.no_uneven else uneven_batch(sft, siggen, torch, stream)
     serving = None if args.no_serve else serving_runs(sft, siggen, torch)
+    noise = None if args.no_noise else noise_robustness(sft, siggen, torch, stream)
 
     if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
         n = args.calib_copy_mib * 2 ** 20 // 4
@@ -361,6 +394,7 @@ def main():
         "accuracy": acc,
         "uneven_batch": uneven,
         "serving": serving,
+        "noise_robustness": noise,
     }
     print(json.dumps(out), flush=True)
 
