@@ -303,22 +303,25 @@ def main():
     # ---- roofline of the dominant kernel (and of every kernel with a byte count)
     work = kernel_work(info)
     per_kernel = {}
+    tpl = {}   # transforms per launch: a batch may be submitted as several pipelined groups
     for name, (byts, flops) in work.items():
         if kern[name]["avg_ms"] > 0:
+            tpl[name] = B * args.steps / kern[name]["launches"]
             avg_s = kern[name]["avg_ms"] * 1e-3
-            per_kernel[name] = {"GBps": byts * B / avg_s / 1e9, "TFLOPs": flops * B / avg_s / 1e12,
-                                "hbm_frac": byts * B / avg_s / 1e9 / HBM_PEAK_GBS}
+            per_kernel[name] = {"GBps": byts * tpl[name] / avg_s / 1e9, "TFLOPs": flops * tpl[name] / avg_s / 1e12,
+                                "hbm_frac": byts * tpl[name] / avg_s / 1e9 / HBM_PEAK_GBS,
+                                "transforms_per_launch": tpl[name]}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     roof = None
     if dom in work and kern[dom]["avg_ms"] > 0:
         byts, flops = work[dom]
         ach = per_kernel[dom]["GBps"]
-        tr = measured_traffic(dom) if B == 256 else None
+        tr = measured_traffic(dom) if tpl[dom] == 64 else None
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None,
                 "traffic_detail": tr,
-                "algorithmic_bytes_per_launch": byts * B, "avg_launch_ms": kern[dom]["avg_ms"],
-                "transforms_per_launch": B}
+                "algorithmic_bytes_per_launch": byts * tpl[dom], "avg_launch_ms": kern[dom]["avg_ms"],
+                "transforms_per_launch": tpl[dom]}
     gb = per_kernel.get("k_gather", {}).get("GBps", 0.0)
 
     # ---- accuracy and CPU baseline (FP64 oracle, bounded sample)

@@ -140,6 +140,20 @@ __device__ __forceinline__ int64_t pos_mod(int64_t x, int64_t m) {
     return r < 0 ? r + m : r;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP: shifts by 1, 2,
+// 4, 8 within each row of 16 lanes, then the row totals broadcast to the
+// following rows (lane 15 to rows 1 and 3, lane 31 to rows 2 and 3).  Every
+// lane of the wave must be active.
+__device__ __forceinline__ int wave_inclusive_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
 // Exclusive scan of data[0..n) (LDS) in place for a kThreads workgroup;
 // returns the total.  Each thread scans a contiguous chunk; the chunk sums are
 // scanned by wave shuffles and one exchange of the wave totals.
@@ -153,11 +167,7 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
     const int end = min(n, beg + chunk);
     int sum = 0;
     for (int i = beg; i < end; ++i) sum += data[i];
-    int x = sum;   // inclusive scan within the wave
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
+    const int x = wave_inclusive_sum(sum);
     if (lane == 63) scratch[wid] = x;
     __syncthreads();
     int base = 0, total = 0;
@@ -717,11 +727,7 @@ __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32
             cnt[q] = r < nb ? hist[nb - 1 - r] : 0;
             loc += cnt[q];
         }
-        int x = loc;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
+        const int x = wave_inclusive_sum(loc);
         if (lane == 63) part[wid] = x;
         __syncthreads();
         int base = 0;
@@ -755,11 +761,7 @@ __device__ int block_exclusive_sum(int v, int32_t* part) {
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    int x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
+    const int x = wave_inclusive_sum(v);
     if (lane == 63) part[wid] = x;
     __syncthreads();
     int base = 0;
@@ -918,13 +920,24 @@ __device__ void emit_heavy_regs(const uint32_t (&hi)[NK], uint64_t valid, LoF lo
         const uint32_t hb = 0xffffffffu - (uint32_t)(mine & 0xffffffffu);
         const int c = (int)(hb & cmask);
         int r = 0;
-        for (int i = 0; i < ct.count; ++i) {
-            const int t2 = ct(c, i);
-            const int o2 = offs[t2];
-            const int o3 = min(o2 + offs[NT + t2], T);
-            for (int e2 = o2; e2 < o3; ++e2) {
-                const uint64_t k2 = hk[e2];
-                r += (k2 > mine && ((0xffffffffu - (uint32_t)(k2 & 0xffffffffu)) & cmask) == (uint32_t)c) ? 1 : 0;
+        for (int i0 = 0; i0 < ct.count; i0 += 8) {   // the entry ranges of 8 class threads at a time
+            int o2[8], o3[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                o2[u] = o3[u] = 0;
+                if (i0 + u < ct.count) {
+                    const int t2 = ct(c, i0 + u);
+                    o2[u] = offs[t2];
+                    o3[u] = offs[NT + t2];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int end = min(o2[u] + o3[u], T);
+                for (int e2 = o2[u]; e2 < end; ++e2) {
+                    const uint64_t k2 = hk[e2];
+                    r += (k2 > mine && ((0xffffffffu - (uint32_t)(k2 & 0xffffffffu)) & cmask) == (uint32_t)c) ? 1 : 0;
+                }
             }
         }
         if (r < depth) cl[c * depth + r] = (int32_t)hb;
