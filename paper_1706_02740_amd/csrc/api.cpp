@@ -145,7 +145,8 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     pl->split = path == 2 || (path == 0 && !fits && !mx_fits);
     pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
     d.vote_bitmap = identify_lds_bytes(d, true) <= lds_cap ? 1 : 0;
-    pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d, d.vote_bitmap != 0);
+    // bit 32: the key vote (a batch takes it when any of its plans needs it)
+    pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d, d.vote_bitmap != 0) | ((size_t)(d.vote_bitmap == 0) << 32);
     pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
     pl->blocks[SFT_KERNEL_GATHER] = gather_blocks(d);
     pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);

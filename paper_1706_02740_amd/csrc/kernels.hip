@@ -140,6 +140,18 @@ __device__ __forceinline__ int64_t pos_mod(int64_t x, int64_t m) {
     return r < 0 ? r + m : r;
 }
 
+// Sum of the wave totals part[0..wid) (NT / 64 LDS values, read together).
+template <int NT>
+__device__ __forceinline__ int waves_before(const int32_t* part, int wid) {
+    int base = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        const int v = part[w];
+        base += w < wid ? v : 0;
+    }
+    return base;
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave with DPP: shifts by 1, 2,
 // 4, 8 within each row of 16 lanes, then the row totals broadcast to the
 // following rows (lane 15 to rows 1 and 3, lane 31 to rows 2 and 3).  Every
@@ -731,7 +743,7 @@ __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32
         if (lane == 63) part[wid] = x;
         __syncthreads();
         int base = 0;
-        for (int w = 0; w < wid; ++w) base += part[w];
+        base = waves_before<NT>(part, wid);
         const int incl = base + x;
         int run = incl - loc;
         if (run < need && incl >= need) {
@@ -755,8 +767,10 @@ __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32
     return prefix;
 }
 
-// Exclusive block-wide prefix sum of one value per thread.  part: LDS int32[NT/64].
-template <int NT>
+// Exclusive block-wide prefix sum of one value per thread.  part: LDS
+// int32[NT/64].  Without the trailing barrier part must not be rewritten
+// before every thread has returned (the caller's next barrier).
+template <int NT, bool TAIL_BARRIER = true>
 __device__ int block_exclusive_sum(int v, int32_t* part) {
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63;
@@ -764,9 +778,8 @@ __device__ int block_exclusive_sum(int v, int32_t* part) {
     const int x = wave_inclusive_sum(v);
     if (lane == 63) part[wid] = x;
     __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wid; ++w) base += part[w];
-    __syncthreads();
+    const int base = waves_before<NT>(part, wid);
+    if (TAIL_BARRIER) __syncthreads();
     return base + x - v;
 }
 
@@ -895,7 +908,7 @@ __device__ void emit_heavy_regs(const uint32_t (&hi)[NK], uint64_t valid, LoF lo
         }
     }
     const int cnt = __popcll(hm);
-    const int ex = block_exclusive_sum<NT>(cnt, part);
+    const int ex = block_exclusive_sum<NT, false>(cnt, part);   // part is not reused in this block
     offs[tid] = ex;
     offs[NT + tid] = cnt;
 #pragma unroll
@@ -1381,6 +1394,10 @@ __device__ __forceinline__ float median_of(const float* v, int K) {
     return med;
 }
 
+// KEYVOTE: the vote compares bin keys with the thresholds (plans whose
+// bitmaps exceed the LDS, or batches that contain one); otherwise it tests the
+// heavy-bin bitmaps.  Both decide the same way.
+template <bool KEYVOTE>
 __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
@@ -1406,7 +1423,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     uint8_t* ccount = reinterpret_cast<uint8_t*>(pre + ((nslots + 2) & ~1));   // [K * s1]
     // heavy-bin bitmaps of the band's K blocks (when they fit the LDS): bit h of
     // block jj at word woff[jj] + h / 32; otherwise the vote compares keys
-    const bool use_bm = d->vote_bitmap != 0;
+    constexpr bool use_bm = !KEYVOTE;
     uint32_t* bm = reinterpret_cast<uint32_t*>(ccount + (((size_t)K * s1 + 3) & ~(size_t)3));
     int woff[kMaxK + 1];
     woff[0] = 0;
@@ -1533,8 +1550,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         int hh[kMaxK];
         int votes = 0;
         const int t_lo = t * G, t_hi = t_lo + G;
-        float er[kMaxK], ei[kMaxK];   // the K bin values, for the median
-        auto read_bins = [&]() {
+        auto read_bins = [&](float* er, float* ei) {
 #pragma unroll
             for (int jj = 0; jj < kMaxK; ++jj) {
                 if (jj < K) {
@@ -1558,7 +1574,8 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 }
             }
         }
-        if (use_bm) {
+        float er[kMaxK], ei[kMaxK];   // the K bin values, for the median
+        if constexpr (use_bm) {
 #pragma unroll
             for (int jj = 0; jj < kMaxK; ++jj) {
                 if (jj < K) {
@@ -1567,7 +1584,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 }
             }
         } else {   // the same heavy test from the bin values: key >= the block's threshold
-            read_bins();
+            read_bins(er, ei);
 #pragma unroll
             for (int jj = 0; jj < kMaxK; ++jj) {
                 if (jj < K) {
@@ -1577,7 +1594,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
             }
         }
         if (2 * votes > K - G) {
-            if (use_bm) read_bins();
+            if constexpr (use_bm) read_bins(er, ei);
             const float zr = median_of(er, K);
             const float zi = median_of(ei, K);
             const float m2 = fmaf(zr, zr, zi * zi);
@@ -1823,8 +1840,8 @@ size_t select_lds_bytes(const SigDesc& d) {
 // for an opt-in.  A rejected request is not an error here: the launch itself
 // reports a size the device cannot hold.
 hipError_t configure_kernels(int max_lds) {
-    const void* ks[8] = {(const void*)k_dft<8, false>, (const void*)k_dft<16, false>, (const void*)k_dft<0, true>,
-                         (const void*)k_identify, (const void*)k_merge, (const void*)k_dft_rows,
+    const void* ks[] = {(const void*)k_dft<8, false>, (const void*)k_dft<16, false>, (const void*)k_dft<0, true>,
+                         (const void*)k_identify<false>, (const void*)k_identify<true>, (const void*)k_merge, (const void*)k_dft_rows,
                          (const void*)k_dft_cols, (const void*)k_select};
     for (const void* k : ks) {
         hipFuncAttributes fa;
@@ -1876,7 +1893,10 @@ hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t
 }
 
 hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(k_identify, dim3(blocks), dim3(kThreads), lds, st, a);
+    // lds carries the byte count in its low 32 bits; bit 32 selects the key vote
+    const size_t bytes = lds & 0xffffffffu;
+    if (lds >> 32) hipLaunchKernelGGL(k_identify<true>, dim3(blocks), dim3(kThreads), bytes, st, a);
+    else hipLaunchKernelGGL(k_identify<false>, dim3(blocks), dim3(kThreads), bytes, st, a);
     return hipGetLastError();
 }
 

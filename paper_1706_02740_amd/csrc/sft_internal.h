@@ -37,7 +37,7 @@ struct SigDesc {
     int64_t lo, hi;         // B = [lo, hi]
     int32_t s, kappa, taps, Q, K, G, s1, log2s1, T, depth, M, Tpow2;
     int32_t accept_cap;     // accepted candidates one band may hold: min(4096, pow2 >= 8 s)
-    int32_t vote_bitmap;    // 1: identify votes from LDS heavy-bin bitmaps (they fit); 0: from bin keys
+    int32_t vote_bitmap;    // 1: the heavy-bin bitmaps of identify fit the LDS; 0: identify must vote from bin keys
     float   inv2sig2;       // 1 / (2 sigma_t^2)
     float   wnorm;          // 1 / (2 pi sigma_t): W(v) = wnorm exp(-v^2 inv2sig2)
     float   gtap[kFastTaps];  // exp(-(i - kappa)^2 inv2sig2), i < taps (taps <= kFastTaps)
