@@ -10,8 +10,8 @@ The oracle is deliberately plain and slow: it follows the steps of
 Algorithm 1 (Section 3) in the paper's order, evaluates the filtered samples
 with the truncated convolution sum of Lemma 10, runs the short DFTs of
 Appendix B with ``numpy.fft`` as the library primitive, and identifies and
-estimates frequencies with the residue/CRT, majority-vote and median reading
-of the inner algorithm (see ``oracle.sft``).  Everything is FP64 / exact
+estimates frequencies with the residue/CRT (or phase-shift), majority-vote and
+median reading of the inner algorithm (see ``oracle.sft``).  Everything is FP64 / exact
 integers.
 
 Modules:
@@ -19,16 +19,17 @@ Modules:
   transform -- the transform itself, with every intermediate exposed
 """
 from .plan import (Params, Plan, make_plan, PRESET_DMSFT6, PRESET_DMSFT4,
-                   PRESET_THEORY)
+                   PRESET_THEORY, IDENT_RESIDUE, IDENT_PHASE)
 from .transform import (node_geometry, window_weight, ghat, filtered_samples,
                   short_dft, heavy_bins, crt, representative_in_band,
-                  class_depth, candidates, vote_count, accepted_by_vote, median_estimate, sft, sft_trace)
+                  class_depth, candidates, vote_count, accepted_by_vote, median_estimate,
+                  phase_frequency, phase_candidates, sft, sft_trace)
 
 __all__ = [
     "Params", "Plan", "make_plan", "PRESET_DMSFT6", "PRESET_DMSFT4",
-    "PRESET_THEORY", "node_geometry", "window_weight", "ghat",
+    "PRESET_THEORY", "IDENT_RESIDUE", "IDENT_PHASE", "node_geometry", "window_weight", "ghat",
     "filtered_samples", "short_dft", "heavy_bins", "crt",
     "representative_in_band", "class_depth", "candidates", "vote_count", "accepted_by_vote",
-    "median_estimate",
+    "median_estimate", "phase_frequency", "phase_candidates",
     "sft", "sft_trace",
 ]

@@ -26,6 +26,12 @@ Readings where the paper is silent (they are the same on both sides):
   p_min the least integer with p_min^G * s1 >= N, and p_1 < ... < p_K the
   K = 2G + 1 smallest odd primes >= max(3, p_min).  Two CRT tuples of G
   moduli each: (1..G) and (G+1..2G).  T = min(2 s, P_1) heavy bins per DFT.
+* identification (line 9's inner algorithm): ``IDENT_RESIDUE`` combines heavy
+  bins of several moduli by the CRT; ``IDENT_PHASE`` reads each heavy bin's
+  frequency from the phase between the bin and the same bin of samples taken
+  one grid step later (the phase-shift family the paper pairs with CLW-DSFT in
+  Section 5, whose inner algorithm it does not print).  Both use the same
+  moduli, heavy bins, majority vote and median.
 """
 from __future__ import annotations
 
@@ -35,6 +41,9 @@ import math
 PRESET_DMSFT6 = 0
 PRESET_DMSFT4 = 1
 PRESET_THEORY = 2
+
+IDENT_RESIDUE = 0
+IDENT_PHASE = 1
 
 
 @dataclasses.dataclass(frozen=True)
@@ -48,6 +57,7 @@ class Params:
     s1_mult: int = 0
     group: int = 0
     heavy_T: int = 0
+    ident: int = IDENT_RESIDUE
 
 
 @dataclasses.dataclass(frozen=True)
@@ -73,6 +83,7 @@ class Plan:
     T: int
     tuples: tuple
     r: float
+    ident: int = IDENT_RESIDUE
 
     @property
     def band_lo(self) -> int:
@@ -106,6 +117,8 @@ def make_plan(N: int, s: int, params: Params = Params()) -> Plan:
     if s < 1 or s > N:
         raise ValueError("s must satisfy 1 <= s <= N")
     preset = params.preset
+    if params.ident not in (IDENT_RESIDUE, IDENT_PHASE):
+        raise ValueError("unknown identification")
     lnN = math.log(N)
     r = 0.0
     if preset in (PRESET_DMSFT6, PRESET_DMSFT4):
@@ -165,4 +178,5 @@ def make_plan(N: int, s: int, params: Params = Params()) -> Plan:
     return Plan(N=N, s=s, preset=preset, kappa=int(kappa), sigma_t=float(sigma_t),
                 beta=float(beta), c1=float(c1), tau=float(tau), alpha=float(alpha),
                 c2=float(c2), Q=int(Q), L=int(L), q=q, s1=s1, G=G, K=K,
-                primes=tuple(primes), P=P, T=int(T), tuples=tuples, r=float(r))
+                primes=tuple(primes), P=P, T=int(T), tuples=tuples, r=float(r),
+                ident=int(params.ident))

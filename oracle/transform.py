@@ -30,6 +30,19 @@ for each band b = 1..Q (Algorithm 1, lines 3-4):
      ghat_{w - q_b} = exp(-c1^2 (w - q_b)^2 / 2) / sqrt(2 pi) (Lemma 2).
 then (line 16) return the s largest |v_w| over all bands, ties to the smaller w.
 
+Phase identification (plan.ident == IDENT_PHASE) replaces steps 4-5:
+  1'. the samples of step 1 are also taken at every node moved one grid step,
+      theta + 2 pi / N: the same window and weights over f[(j'+1+i) mod N];
+  2'. their short DFTs E'_b[j].  A bin h of modulus j that holds one
+      frequency w (ghat-weighted) has E'[h] / E[h] = exp(2 pi i w / N), and
+      w = h (mod P_j) is known, so the phase only has to single out one member
+      of that residue class (a tolerance of pi P_j / N radians);
+  4'. candidates: for every heavy bin, the w in B with w = h (mod P_j) whose
+      angle 2 pi w / N lies circularly nearest to arg(E'[h] conj(E[h]))
+      (ties to the smaller w), over all moduli, duplicates merged;
+  5'. vote: keep w if more than half of all K moduli have (w mod P_j) among
+      their heavy bins.
+
 Frequencies are integers in B = (-ceil(N/2), floor(N/2)]; coefficients are
 those of f_j = sum_w c_w exp(2 pi i w j / N).
 """
@@ -40,7 +53,7 @@ import math
 
 import numpy as np
 
-from .plan import Plan
+from .plan import IDENT_PHASE, Plan
 
 COMBO_CAP = 64
 
@@ -83,8 +96,12 @@ def ghat(plan: Plan, n) -> np.ndarray:
     return np.exp(-(plan.c1 ** 2) * n * n / 2.0) / math.sqrt(2.0 * math.pi)
 
 
-def filtered_samples(plan: Plan, f: np.ndarray, b: int, j: int) -> np.ndarray:
-    """S_b at the nodes of modulus j (Algorithm 1, line 7; Lemma 10's window)."""
+def filtered_samples(plan: Plan, f: np.ndarray, b: int, j: int, shift: int = 0) -> np.ndarray:
+    """S_b at the nodes of modulus j (Algorithm 1, line 7; Lemma 10's window).
+
+    shift moves every node by that many grid steps (theta + 2 pi shift / N):
+    the nearest grid index moves with it and the offset u does not, so the
+    weights stay those of the unshifted node."""
     f = np.asarray(f, dtype=np.complex128)
     N = plan.N
     P = plan.P[j]
@@ -94,7 +111,7 @@ def filtered_samples(plan: Plan, f: np.ndarray, b: int, j: int) -> np.ndarray:
     S = np.zeros(P, dtype=np.complex128)
     for i in range(-plan.kappa, plan.kappa + 1):
         v = u - i
-        S += f[np.mod(jp + i, N)] * window_weight(plan, v) * np.exp(2j * math.pi * q * v / N)
+        S += f[np.mod(jp + shift + i, N)] * window_weight(plan, v) * np.exp(2j * math.pi * q * v / N)
     return S
 
 
@@ -179,6 +196,37 @@ def candidates(plan: Plan, heavy, E) -> dict:
     return dict(sorted(found.items()))
 
 
+def phase_frequency(plan: Plan, j: int, h: int, e: complex, e_shift: complex):
+    """The w in B with w = h (mod P_j) whose angle 2 pi w / N is circularly
+    nearest to arg(e_shift conj(e)), ties to the smaller w; None if B holds no
+    member of the class.  Every member of the class is tried."""
+    N = plan.N
+    P = plan.P[j]
+    x = float(np.angle(complex(e_shift) * complex(e).conjugate())) * N / (2.0 * math.pi)
+    lo, hi = plan.band_lo, plan.band_hi
+    m_lo = -((h - lo) // P)          # least m with h + m P >= lo
+    m_hi = (hi - h) // P             # largest m with h + m P <= hi
+    if m_hi < m_lo:
+        return None
+    ws = h + P * np.arange(m_lo, m_hi + 1, dtype=np.int64)
+    d = ws.astype(np.float64) - x
+    dist = np.minimum(np.abs(d), np.minimum(np.abs(d - N), np.abs(d + N)))
+    best = np.lexsort((ws, dist))[0]
+    return int(ws[best])
+
+
+def phase_candidates(plan: Plan, heavy, E, E_shift) -> list:
+    """Candidate frequencies of one band: phase_frequency of every heavy bin of
+    every modulus, duplicates merged, ascending."""
+    found = set()
+    for j in range(plan.K):
+        for h in heavy[j]:
+            w = phase_frequency(plan, j, int(h), E[j][h], E_shift[j][h])
+            if w is not None:
+                found.add(w)
+    return sorted(found)
+
+
 def vote_count(plan: Plan, heavy_sets, w: int, exclude=()) -> int:
     """Number of moduli j (outside `exclude`) whose heavy bins contain w mod P_j."""
     return sum(1 for j in range(plan.K) if j not in exclude and (w % plan.P[j]) in heavy_sets[j])
@@ -200,11 +248,20 @@ def _band(plan: Plan, f: np.ndarray, b: int, keep: bool):
     E = [short_dft(Sj) for Sj in S]
     heavy = [heavy_bins(Ej, plan.T) for Ej in E]
     heavy_sets = [set(int(h) for h in Hj) for Hj in heavy]
-    cands = candidates(plan, heavy, E)
     accepted = []
-    for w, tuples in cands.items():
-        if accepted_by_vote(plan, heavy_sets, w, tuples):
-            accepted.append((w, median_estimate(plan, E, w)))
+    S2 = E2 = None
+    if plan.ident == IDENT_PHASE:
+        S2 = [filtered_samples(plan, f, b, j, shift=1) for j in range(plan.K)]
+        E2 = [short_dft(Sj) for Sj in S2]
+        cands = phase_candidates(plan, heavy, E, E2)
+        for w in cands:
+            if 2 * vote_count(plan, heavy_sets, w) > plan.K:
+                accepted.append((w, median_estimate(plan, E, w)))
+    else:
+        cands = candidates(plan, heavy, E)
+        for w, tuples in cands.items():
+            if accepted_by_vote(plan, heavy_sets, w, tuples):
+                accepted.append((w, median_estimate(plan, E, w)))
     # Algorithm 1, line 9: the s-sparse output of the inner algorithm
     r_temp = sorted(accepted, key=lambda wz: (-abs(wz[1]), wz[0]))[: plan.s]
     # lines 10-11: band test and division by the modulated filter's coefficient
@@ -216,7 +273,7 @@ def _band(plan: Plan, f: np.ndarray, b: int, keep: bool):
     info = None
     if keep:
         info = dict(S=S, E=E, heavy=heavy, candidates=cands, accepted=accepted,
-                    r_temp=r_temp, kept=out)
+                    r_temp=r_temp, kept=out, S_shift=S2, E_shift=E2)
     return out, info
 
 

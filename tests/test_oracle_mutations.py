@@ -2,7 +2,8 @@
 catch each one: a flipped modulation sign, a dropped window tap, a shifted
 node rounding, a missing DFT normalisation, a wrong tie rule, a mean in place
 of the median, a transposed CRT pairing, a wrong exponent in ghat, an
-inclusive band edge."""
+inclusive band edge, a shift in the wrong direction, a phase read without
+wrap-around, a tie sent to the larger frequency."""
 import math
 
 import numpy as np
@@ -12,6 +13,7 @@ import oracle
 import oracle.transform as osft
 import tests.test_oracle_pins as pins
 import tests.test_oracle_end_to_end as e2e
+import tests.test_oracle_phase as phase
 
 
 def _bad_samples_sign(plan, f, b, j):
@@ -82,6 +84,37 @@ def _bad_vote_all_moduli(plan, heavy_sets, w, tuples):
     return 2 * sum((w % plan.P[j]) in heavy_sets[j] for j in range(plan.K)) > plan.K
 
 
+_orig_samples = osft.filtered_samples
+_orig_phase = osft.phase_frequency
+
+
+def _bad_shift_sign(plan, f, b, j, shift=0):
+    return _orig_samples(plan, f, b, j, shift=-shift)
+
+
+def _bad_phase_no_wrap(plan, j, h, e, e_shift):
+    """Linear instead of circular distance to the phase's frequency."""
+    N, P = plan.N, plan.P[j]
+    x = float(np.angle(complex(e_shift) * complex(e).conjugate())) * N / (2.0 * math.pi)
+    best = None
+    for m in range(-((h - plan.band_lo) // P), (plan.band_hi - h) // P + 1):
+        w = h + m * P
+        if best is None or (abs(w - x), w) < best:
+            best = (abs(w - x), w)
+    return None if best is None else best[1]
+
+
+def _bad_phase_ties_up(plan, j, h, e, e_shift):
+    w = _orig_phase(plan, j, h, e, e_shift)
+    if w is None:
+        return None
+    x = float(np.angle(complex(e_shift) * complex(e).conjugate())) * plan.N / (2.0 * math.pi)
+    up = w + plan.P[j]
+    if up <= plan.band_hi and abs(up - x) == abs(w - x):
+        return up
+    return w
+
+
 MUTATIONS = [
     ("filtered_samples", _bad_samples_sign, lambda: pins.test_filtered_samples_closed_form(0)),
     ("filtered_samples", _bad_samples_short_window, pins.test_window_extent_with_a_unit_impulse),
@@ -95,6 +128,10 @@ MUTATIONS = [
     ("ghat", _bad_ghat, e2e.test_band_edge_frequencies),
     ("accepted_by_vote", _bad_vote_all_moduli, e2e.test_candidates_equal_bruteforce_definition),
     ("accepted_by_vote", _bad_vote_all_moduli, e2e.test_ghost_combinations_are_rejected),
+    ("filtered_samples", _bad_shift_sign, lambda: phase.test_shifted_samples_closed_form(4096, 6)),
+    ("filtered_samples", _bad_shift_sign, lambda: phase.test_one_sparse_bins_carry_the_frequency(3001, 3)),
+    ("phase_frequency", _bad_phase_no_wrap, lambda: phase.test_phase_frequency_worked_examples(100, 12, 5, 0.499, -43)),
+    ("phase_frequency", _bad_phase_ties_up, lambda: phase.test_phase_frequency_worked_examples(100, 8, 21, 0.25, 21)),
 ]
 
 
