@@ -60,6 +60,10 @@ extern "C" {
 #define SFT_PRESET_DMSFT4 1  /* kappa = 4 (9 taps); Section 5's DMSFT-4 window */
 #define SFT_PRESET_THEORY 2  /* beta = 6 sqrt(r), kappa = ceil(6 r ln N / (sqrt(2) pi)) + 1 (Theorem 4) */
 
+/* identification of the inner algorithm (Algorithm 1, line 9) */
+#define SFT_IDENT_RESIDUE 0  /* heavy bins of several moduli combined by the CRT, then a majority vote */
+#define SFT_IDENT_PHASE   1  /* each heavy bin's frequency from its phase against samples one grid step later */
+
 #define SFT_MAX_MODULI 15    /* K = 2G + 1 <= 15 */
 #define SFT_MAX_BANDS  128
 
@@ -76,6 +80,15 @@ extern "C" {
  * else in LDS on the vector ALUs when it fits, else the split path),
  * 1 = in LDS on the vector ALUs, 2 = split, 3 = in LDS on the matrix cores.
  * Paths 1 and 2 give bitwise equal results; path 3 sums in another order.
+ * ident chooses the identification (SFT_IDENT_*).  SFT_IDENT_PHASE is the
+ * phase-shift family that Section 5 pairs with CLW-DSFT (whose inner algorithm
+ * the paper does not print): the filtered samples are also taken at every node
+ * moved one grid step (x + 2 pi / N), their short DFTs E' are formed too, and a
+ * heavy bin h of modulus j yields the w in B with w = h (mod P_j) whose angle
+ * 2 pi w / N lies circularly nearest to arg(E'[h] conj(E[h])) (FP64; ties to
+ * the smaller w).  Candidates of all moduli are merged and kept if more than
+ * half of all K moduli hold a heavy bin at w; the estimate is the same median.
+ * It doubles the samples and short DFTs.
  */
 typedef struct sft_params {
     int32_t preset;
@@ -87,6 +100,7 @@ typedef struct sft_params {
     int32_t group;
     int32_t heavy_T;
     int32_t dft_path;
+    int32_t ident;
 } sft_params;
 
 /*
@@ -109,7 +123,7 @@ typedef struct sft_plan_info {
     int32_t K;
     int32_t T;
     int32_t depth;      /* heaviest bins per residue class combined by the CRT step */
-    int32_t reserved;
+    int32_t ident;      /* SFT_IDENT_* */
     double  sigma_t;
     double  beta;
     double  c1;
@@ -190,12 +204,16 @@ SFT_API int sft_plan_status(sft_plan_t plan, int32_t* flags);
  *                      (j*Q + b)*T, in ascending Good-Thomas position.
  *   SFT_FETCH_BANDS    per band b: int32 count at [b], then (int64 w, double re,
  *                      double im) records; see the library documentation.
+ *   SFT_FETCH_SAMPLES_SHIFTED, SFT_FETCH_BINS_SHIFTED  (SFT_IDENT_PHASE plans)
+ *                      as SAMPLES and BINS for the nodes moved one grid step.
  * bytes_needed (may be NULL) receives the size; dst may be NULL to query.
  */
 #define SFT_FETCH_SAMPLES 0
 #define SFT_FETCH_BINS    1
 #define SFT_FETCH_HEAVY   2
 #define SFT_FETCH_BANDS   3
+#define SFT_FETCH_SAMPLES_SHIFTED 4
+#define SFT_FETCH_BINS_SHIFTED    5
 SFT_API int sft_plan_fetch(const sft_plan_t plan, int32_t what, void* dst, size_t bytes,
                    size_t* bytes_needed);
 

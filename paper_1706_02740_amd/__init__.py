@@ -34,10 +34,16 @@ PRESET_DMSFT4 = 1
 PRESET_THEORY = 2
 PRESETS = {"dmsft6": PRESET_DMSFT6, "dmsft4": PRESET_DMSFT4, "theory": PRESET_THEORY}
 
+IDENT_RESIDUE = 0
+IDENT_PHASE = 1
+IDENTS = {"residue": IDENT_RESIDUE, "phase": IDENT_PHASE}
+
 FETCH_SAMPLES = 0
 FETCH_BINS = 1
 FETCH_HEAVY = 2
 FETCH_BANDS = 3
+FETCH_SAMPLES_SHIFTED = 4
+FETCH_BINS_SHIFTED = 5
 
 KERNEL_GATHER = 0
 KERNEL_DFT = 1
@@ -70,7 +76,8 @@ class SftError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("preset", ctypes.c_int32), ("kappa", ctypes.c_int32), ("sigma_t", ctypes.c_double),
                 ("tau", ctypes.c_double), ("r", ctypes.c_double), ("s1_mult", ctypes.c_int32),
-                ("group", ctypes.c_int32), ("heavy_T", ctypes.c_int32), ("dft_path", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("heavy_T", ctypes.c_int32), ("dft_path", ctypes.c_int32),
+                ("ident", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -78,7 +85,7 @@ class PlanInfo(ctypes.Structure):
                 ("kappa", ctypes.c_int32), ("Q", ctypes.c_int32), ("L", ctypes.c_int64),
                 ("q_first", ctypes.c_int64), ("s1", ctypes.c_int32), ("G", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("T", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("sigma_t", ctypes.c_double), ("beta", ctypes.c_double),
+                ("ident", ctypes.c_int32), ("sigma_t", ctypes.c_double), ("beta", ctypes.c_double),
                 ("c1", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("c2", ctypes.c_double), ("r", ctypes.c_double),
                 ("primes", ctypes.c_int32 * MAX_MODULI), ("reserved2", ctypes.c_int32),
@@ -136,20 +143,23 @@ def require_device():
 
 
 def make_params(preset=PRESET_DMSFT6, kappa=0, sigma_t=0.0, tau=0.0, r=0.0, s1_mult=0,
-                group=0, heavy_T=0, dft_path=0) -> Params:
+                group=0, heavy_T=0, dft_path=0, ident=IDENT_RESIDUE) -> Params:
     if isinstance(preset, str):
         preset = PRESETS[preset]
+    if isinstance(ident, str):
+        ident = IDENTS[ident]
     p = Params()
     _check(load_library().sft_params_default(ctypes.byref(p), int(preset)))
     p.kappa, p.sigma_t, p.tau, p.r = int(kappa), float(sigma_t), float(tau), float(r)
     p.s1_mult, p.group, p.heavy_T, p.dft_path = int(s1_mult), int(group), int(heavy_T), int(dft_path)
+    p.ident = int(ident)
     return p
 
 
 def _info_dict(info: PlanInfo) -> dict:
     K = info.K
     d = {name: getattr(info, name) for name, _ in PlanInfo._fields_
-         if name not in ("primes", "P", "reserved", "reserved2")}
+         if name not in ("primes", "P", "reserved2")}
     d["primes"] = tuple(int(info.primes[j]) for j in range(K))
     d["P"] = tuple(int(info.P[j]) for j in range(K))
     d["q"] = tuple(info.q_first + 2 * b * info.L for b in range(info.Q))
@@ -229,7 +239,7 @@ class Plan:
         _check(lib.sft_plan_fetch(self._h, int(what), None, 0, ctypes.byref(need)))
         buf = np.empty(need.value, dtype=np.uint8)
         _check(lib.sft_plan_fetch(self._h, int(what), ctypes.c_void_p(buf.ctypes.data), need.value, None))
-        if what in (FETCH_SAMPLES, FETCH_BINS):
+        if what in (FETCH_SAMPLES, FETCH_BINS, FETCH_SAMPLES_SHIFTED, FETCH_BINS_SHIFTED):
             return buf.view(np.complex64)
         if what == FETCH_HEAVY:
             return buf.view(np.int32)

@@ -54,6 +54,8 @@ static IoDesc carve(void* base, const WorkspaceLayout& wl) {
     char* p = static_cast<char*>(base);
     io.S = reinterpret_cast<float2*>(p); p += wl.S;
     io.E = reinterpret_cast<float2*>(p); p += wl.E;
+    io.S2 = wl.S2 ? reinterpret_cast<float2*>(p) : nullptr; p += wl.S2;
+    io.E2 = wl.E2 ? reinterpret_cast<float2*>(p) : nullptr; p += wl.E2;
     io.H = reinterpret_cast<int32_t*>(p); p += wl.H;
     io.thr = reinterpret_cast<uint64_t*>(p); p += wl.thr;
     io.CL = reinterpret_cast<int32_t*>(p); p += wl.CL;
@@ -145,8 +147,10 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     pl->split = path == 2 || (path == 0 && !fits && !mx_fits);
     pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
     d.vote_bitmap = identify_lds_bytes(d, true) <= lds_cap ? 1 : 0;
-    // bit 32: the key vote (a batch takes it when any of its plans needs it)
-    pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d, d.vote_bitmap != 0) | ((size_t)(d.vote_bitmap == 0) << 32);
+    // bit 32: the key vote; bit 33: phase identification (a batch takes each
+    // when any of its plans needs it)
+    pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d, d.vote_bitmap != 0) | ((size_t)(d.vote_bitmap == 0) << 32) |
+                                   ((size_t)d.phase << 33);
     pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
     pl->blocks[SFT_KERNEL_GATHER] = gather_blocks(d);
     pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);
@@ -484,8 +488,9 @@ int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* 
         wsoff[i] = ws_total;
         ws_total += p->wl.total;
         for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
-            if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes)
-                const size_t hi = std::max(p->lds[k] >> 32, lds[k] >> 32);
+            if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes); identify's flags: union
+                const size_t hi = k == SFT_KERNEL_IDENTIFY ? (p->lds[k] >> 32) | (lds[k] >> 32)
+                                                           : std::max(p->lds[k] >> 32, lds[k] >> 32);
                 const size_t lo = std::max(p->lds[k] & 0xffffffffu, lds[k] & 0xffffffffu);
                 lds[k] = (hi << 32) | lo;
             }
@@ -584,6 +589,12 @@ int sft_plan_fetch(const sft_plan_t plan, int32_t what, void* dst, size_t bytes,
         case SFT_FETCH_BINS: src = plan->ws_io.E; need = (size_t)in.Q * in.M * 8; break;
         case SFT_FETCH_HEAVY: src = plan->ws_io.H; need = (size_t)in.K * in.Q * in.T * 4; break;
         case SFT_FETCH_BANDS: need = (size_t)in.Q * 4 + (size_t)in.Q * in.s * 24; break;
+        case SFT_FETCH_SAMPLES_SHIFTED:
+        case SFT_FETCH_BINS_SHIFTED:
+            if (in.ident != SFT_IDENT_PHASE) return fail(SFT_EINVAL, "shifted samples exist for phase identification only");
+            src = what == SFT_FETCH_SAMPLES_SHIFTED ? plan->ws_io.S2 : plan->ws_io.E2;
+            need = (size_t)in.Q * in.M * 8;
+            break;
         default: return fail(SFT_EINVAL, "unknown fetch kind");
     }
     if (bytes_needed) *bytes_needed = need;

@@ -212,6 +212,9 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
 // band in between.  TAPS > 0 fixes 2 kappa + 1 at compile time (the window is
 // loaded before any arithmetic); TAPS == 0 reads it from the plan.  Both forms
 // perform the same operations in the same order, so their results are equal.
+// Phase identification also needs the samples at the node moved one grid step
+// (t + 1): the window centre moves to j' + 1 and u stays, so a second pass
+// with the same weights writes them to S2.
 
 constexpr int kPhaseAnchor = 8;
 
@@ -272,34 +275,14 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
     const float inv2sig2 = d->inv2sig2;
     const float wnorm = d->wnorm;
     const GLOBAL float2* __restrict__ f = glb(io.f);
-    GLOBAL float2* __restrict__ S = glb(io.S) + (size_t)Q * d->Moff[j] + l;
+    const size_t soff = (size_t)Q * d->Moff[j] + l;
     const CONSTANT float* rate = cst(d->rate);
     const float step_rate = d->a_step;
-    const bool interior = (jp - kappa >= 0) && (jp + kappa < N);
+    const int nshift = d->phase;   // 0, or 1: also the node moved one grid step
 
     if constexpr (TAPS > 0) {
         static_assert(TAPS <= kFastTaps, "tap table");
         constexpr int KP = (TAPS - 1) / 2;
-        float2 x[TAPS];
-        if (interior) {   // the window in 16-byte pieces (8-byte aligned)
-            typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
-            const GLOBAL f4u* w4 = (const GLOBAL f4u*)(f + (jp - kappa));
-#pragma unroll
-            for (int i = 0; i + 1 < TAPS; i += 2) {
-                const f4u v = w4[i >> 1];
-                x[i] = make_float2(v.x, v.y);
-                x[i + 1] = make_float2(v.z, v.w);
-            }
-            if (TAPS & 1) x[TAPS - 1] = ld2(f + (jp - kappa + TAPS - 1));
-        } else {
-#pragma unroll
-            for (int i = 0; i < TAPS; ++i) {
-                int64_t idx = jp - kappa + i;
-                if (idx < 0) idx += N;
-                else if (idx >= N) idx -= N;
-                x[i] = ld2(f + idx);
-            }
-        }
         // W((delta - o P) / P) = wnorm exp(-(u - o)^2 c), o = i - kappa, c = inv2sig2,
         //   = [wnorm exp(-u^2 c)] [exp(-o^2 c)] r^o,  r = exp(2 u c)
         const float e0 = wnorm * expf(-u * u * inv2sig2);
@@ -314,6 +297,29 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             rn *= ri;
             w[KP + o] = e0 * d->gtap[KP + o] * rp;
             w[KP - o] = e0 * d->gtap[KP - o] * rn;
+        }
+        for (int sh = 0;; ++sh) {
+        const int64_t jc = jp + sh;   // window centre
+        GLOBAL float2* __restrict__ S = glb(sh ? io.S2 : io.S) + soff;
+        float2 x[TAPS];
+        if ((jc - kappa >= 0) && (jc + kappa < N)) {   // the window in 16-byte pieces (8-byte aligned)
+            typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
+            const GLOBAL f4u* w4 = (const GLOBAL f4u*)(f + (jc - kappa));
+#pragma unroll
+            for (int i = 0; i + 1 < TAPS; i += 2) {
+                const f4u v = w4[i >> 1];
+                x[i] = make_float2(v.x, v.y);
+                x[i + 1] = make_float2(v.z, v.w);
+            }
+            if (TAPS & 1) x[TAPS - 1] = ld2(f + (jc - kappa + TAPS - 1));
+        } else {
+#pragma unroll
+            for (int i = 0; i < TAPS; ++i) {
+                int64_t idx = jc - kappa + i;
+                if (idx < 0) idx += N;
+                else if (idx >= N) idx -= N;
+                x[i] = ld2(f + idx);
+            }
         }
 #pragma unroll
         for (int i = 0; i < TAPS; ++i) x[i] = make_float2(x[i].x * w[i], x[i].y * w[i]);
@@ -351,6 +357,8 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                 }
             }
         }
+        if (sh >= nshift) break;
+        }
     } else {
         // the same weights as the compile-time kernels, bit for bit: r^|o| by
         // |o| multiplications from 1 in the same order
@@ -366,6 +374,10 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             for (int k = 0; k < (o > 0 ? o : -o); ++k) pw *= rr;
             return e0 * gt * pw;
         };
+        for (int sh = 0; sh <= nshift; ++sh) {
+        const int64_t jc = jp + sh;   // window centre
+        const bool interior = (jc - kappa >= 0) && (jc + kappa < N);
+        GLOBAL float2* __restrict__ S = glb(sh ? io.S2 : io.S) + soff;
         for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
             const int nb = min(kBandChunk, Q - b0);
             float2 acc[kBandChunk];
@@ -373,7 +385,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = make_float2(0.f, 0.f);
             const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * taps;
             for (int i = 0; i < taps; ++i) {
-                int64_t idx = jp - kappa + i;
+                int64_t idx = jc - kappa + i;
                 if (!interior) {
                     if (idx < 0) idx += N;
                     else if (idx >= N) idx -= N;
@@ -390,6 +402,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                 }
             }
             store_bands(S, P, b0, nb, acc, u, rate, step_rate);
+        }
         }
     }
 }
@@ -1061,8 +1074,12 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const int tid = (int)threadIdx.x;
     const int Q = d->Q;
     const int K = d->K;
-    const int j = at.blk / Q;
-    const int b = at.blk - j * Q;
+    // blocks K Q .. 2 K Q - 1 (phase identification): the bins of the samples
+    // at the nodes moved one grid step, transformed and stored only
+    const bool shifted = at.blk >= K * Q;
+    const int blk0 = shifted ? at.blk - K * Q : at.blk;
+    const int j = blk0 / Q;
+    const int b = blk0 - j * Q;
     const int p = d->p[j];
     const int P = d->P[j];
     const int s1 = d->s1;
@@ -1080,7 +1097,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [T]
     int32_t* cl = reinterpret_cast<int32_t*>(hk + d->T);        // [s1 depth]
 
-    const GLOBAL float2* __restrict__ S = glb(io.S) + base;
+    const GLOBAL float2* __restrict__ S = glb(shifted ? io.S2 : io.S) + base;
     if constexpr (MX) {
         // every load of the block in flight at once: samples, twiddles, the
         // p-point step's A operands (to LDS in place of the cosine/sine table)
@@ -1109,7 +1126,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     fft_rows<NT, 64, 64>(buf, p, s1, lg, tw);
 
     // step B
-    GLOBAL float2* __restrict__ E = glb(io.E) + base;
+    GLOBAL float2* __restrict__ E = glb(shifted ? io.E2 : io.E) + base;
     const float scale = 1.0f / (float)P;
     const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
     const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
@@ -1193,6 +1210,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         valid |= (uint64_t)1 << (NK - 1);
     }
     }
+    if (shifted) return;   // uniform over the block
     // Good-Thomas position of slot q of thread th
     auto pos_of = [&](int q, int th) -> int {
         if constexpr (MT > 0) {
@@ -1255,8 +1273,13 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     const int s1 = d->s1;
     const int lg = d->log2s1;
     const int rows_per = max(1, kRowElems >> lg);
+    // blocks past the first set (phase identification): the samples at the
+    // nodes moved one grid step
+    int nrows1 = 0;
+    for (int jj = 0; jj < d->K; ++jj) nrows1 += d->Q * ((d->p[jj] + rows_per - 1) / rows_per);
+    const bool shifted = at.blk >= nrows1;
     int j, b, chunk;
-    split_rows_where(d, at.blk, rows_per, j, b, chunk);
+    split_rows_where(d, shifted ? at.blk - nrows1 : at.blk, rows_per, j, b, chunk);
     const int p = d->p[j];
     const int r0 = chunk * rows_per;
     const int rows = min(rows_per, p - r0);
@@ -1264,7 +1287,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     float2* buf = reinterpret_cast<float2*>(smem);
     float2* tw = buf + ((size_t)rows_per << lg);
     const int n = rows << lg;
-    const GLOBAL float2* __restrict__ S = glb(io.S) + base;
+    const GLOBAL float2* __restrict__ S = glb(shifted ? io.S2 : io.S) + base;
     copy_to_lds<kThreads, 8>(buf, S, n);
     for (int i = tid; i < (s1 >> 1); i += kThreads) {   // the full circle: W^(m + s1/2) = -W^m
         const float2 w = ld2(glb(d->tw_s1) + i);
@@ -1278,7 +1301,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
         fft_rows<kThreads, kRowElems / 128, kRowElems / 64>(buf, rows, s1, lg, tw);
     else
         fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
-    GLOBAL float2* __restrict__ X = glb(io.E) + base;   // the bins' buffer holds the step-A result
+    GLOBAL float2* __restrict__ X = glb(shifted ? io.E2 : io.E) + base;   // the bins' buffer holds the step-A result
     for (int i = tid; i < n; i += kThreads) st2(X + i, buf[i]);
 }
 
@@ -1295,6 +1318,8 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     const int C = min(kColChunk, s1);
     const int nc = s1 / C;
     int blk = at.blk;
+    const bool shifted = blk >= d->K * Q * nc;   // phase identification: the shifted samples' bins
+    if (shifted) blk -= d->K * Q * nc;
     const int j = blk / (Q * nc);
     blk -= j * Q * nc;
     const int b = blk / nc;
@@ -1306,7 +1331,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
     float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]
     float2* trig = tile + (size_t)pmax * C;
-    GLOBAL float2* __restrict__ E = glb(io.E) + base;
+    GLOBAL float2* __restrict__ E = glb(shifted ? io.E2 : io.E) + base;
     constexpr int U = 8;   // loads of a thread in flight before its LDS writes
     for (int i0 = tid; i0 < p * C; i0 += U * kThreads) {
         float2 v[U];
@@ -1394,10 +1419,41 @@ __device__ __forceinline__ float median_of(const float* v, int K) {
     return med;
 }
 
+// Phase identification: bin h of a modulus of length P holds e (samples at the
+// nodes) and e2 (the nodes moved one grid step); for one dominant frequency w,
+// e2 / e = exp(2 pi i w / N).  Returns the w in B = [lo, hi] with w = h (mod P)
+// whose angle 2 pi w / N is circularly nearest to arg(e2 conj(e)), ties to the
+// smaller w, in FP64; false if B holds no member of the class.  The nearest
+// member lies next to the rounded quotient for x, x - N or x + N.
+__device__ bool phase_frequency(float2 e, float2 e2, int h, int P, int64_t N, int64_t lo, int64_t hi, int64_t& w) {
+    constexpr double kTwoPi = 6.283185307179586;
+    const double re = (double)e2.x * (double)e.x + (double)e2.y * (double)e.y;
+    const double im = (double)e2.y * (double)e.x - (double)e2.x * (double)e.y;
+    const double x = atan2(im, re) * (double)N / kTwoPi;
+    bool found = false;
+    double best = 0.0;
+    for (int sh = -1; sh <= 1; ++sh) {
+        const double xs = x + (double)sh * (double)N;
+        const int64_t m0 = (int64_t)floor((xs - (double)h) / (double)P + 0.5);
+        for (int dm = -1; dm <= 1; ++dm) {
+            const int64_t c = (int64_t)h + (m0 + dm) * (int64_t)P;
+            if (c < lo || c > hi) continue;
+            const double dist = fabs((double)c - xs);
+            if (!found || dist < best || (dist == best && c < w)) {
+                found = true;
+                best = dist;
+                w = c;
+            }
+        }
+    }
+    return found;
+}
+
 // KEYVOTE: the vote compares bin keys with the thresholds (plans whose
 // bitmaps exceed the LDS, or batches that contain one); otherwise it tests the
-// heavy-bin bitmaps.  Both decide the same way.
-template <bool KEYVOTE>
+// heavy-bin bitmaps.  Both decide the same way.  PHASE: the launch may hold
+// plans with phase identification (taken per transform).
+template <bool KEYVOTE, bool PHASE>
 __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
@@ -1413,6 +1469,8 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     const int depth = d->depth;
     const int64_t lo = d->lo, hi = d->hi;
     const int nslots = 2 * s1;
+    const bool phase = PHASE && d->phase != 0;
+    const int T = d->T;
 
     const int acap = d->accept_cap;
     uint64_t* akey = reinterpret_cast<uint64_t*>(smem);
@@ -1433,6 +1491,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     __shared__ uint64_t sh_thr[kMaxK];   // the blocks' thresholds (key vote)
 
     const GLOBAL int32_t* __restrict__ CLall = glb(io.CL);
+    const GLOBAL int32_t* __restrict__ Hall = glb(io.H);
     const GLOBAL float2* __restrict__ Eall = glb(io.E);
     const size_t cl_stride = (size_t)s1 * depth;   // one (modulus, band) block of class lists
 
@@ -1446,10 +1505,9 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         // (jj, b) (its min(T, P_jj) entries of H, unordered); a thread's loads of
         // a round are all issued before their first use
         constexpr int U = 4;
-        const int T = d->T;
-        const GLOBAL int32_t* __restrict__ Hall = glb(io.H);
         const int nh = use_bm ? K * T : 0;
-        for (int i0 = tid; i0 < K * s1 || i0 < nh; i0 += U * kThreads) {
+        const int ncl = phase ? 0 : K * s1;   // class lists: residue identification only
+        for (int i0 = tid; i0 < ncl || i0 < nh; i0 += U * kThreads) {
             int32_t hv[U];
             int32_t lv[U][kMaxDepth];
 #pragma unroll
@@ -1463,7 +1521,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 }
 #pragma unroll
                 for (int e = 0; e < kMaxDepth; ++e) lv[u][e] = -1;
-                if (i < K * s1) {
+                if (i < ncl) {
                     const GLOBAL int32_t* cl =
                         CLall + (size_t)((i >> lg) * Q + b) * cl_stride + (size_t)(i & (s1 - 1)) * depth;
 #pragma unroll
@@ -1478,7 +1536,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                     const int jj = i / T;
                     atomicOr(&bm[woff[jj] + (hv[u] >> 5)], 1u << (hv[u] & 31));
                 }
-                if (i < K * s1) {
+                if (i < ncl) {
                     int n = 0;
 #pragma unroll
                     for (int e = 0; e < kMaxDepth; ++e) n += lv[u][e] >= 0 ? 1 : 0;
@@ -1490,7 +1548,8 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     __syncthreads();
 
     // 1. combinations per (tuple, class) slot: product of the class-list lengths
-    for (int slot = tid; slot < nslots; slot += kThreads) {
+    // (phase identification: one candidate per heavy bin, K T of them)
+    for (int slot = tid; slot < nslots && !phase; slot += kThreads) {
         const int t = slot >> lg;
         const int ac = slot & (s1 - 1);
         int cnt = 1;
@@ -1499,13 +1558,23 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     }
     if (tid == 0) sh_cnt = 0;
     __syncthreads();
-    const int total = block_exclusive_scan(pre, nslots, scratch);
+    const int total = phase ? K * T : block_exclusive_scan(pre, nslots, scratch);
     if (tid == 0) pre[nslots] = total;
     __syncthreads();
 
     // 2. candidates -> vote -> median
     const bool small_n = d->N <= ((int64_t)1 << 31);   // then B lies in the int32 range
     for (int c = tid; c < total; c += kThreads) {
+        int64_t w;
+        int t = 0, jp = 0;   // CRT tuple (residue identification); producing modulus (phase)
+        if (PHASE && phase) {
+            jp = c / T;
+            const int e = c - jp * T;
+            const int h0 = Hall[(size_t)(jp * Q + b) * T + e];
+            const size_t at0 = (size_t)Q * d->Moff[jp] + (size_t)b * d->P[jp] +
+                               ((size_t)(h0 % d->p[jp]) << lg) + (size_t)(h0 & (s1 - 1));
+            if (!phase_frequency(ld2(Eall + at0), ld2(glb(io.E2) + at0), h0, d->P[jp], d->N, lo, hi, w)) continue;
+        } else {
         int l0 = 0, h0 = nslots - 1;   // last slot with pre[slot] <= c
         while (l0 < h0) {
             const int mid = (l0 + h0 + 1) >> 1;
@@ -1513,7 +1582,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         }
         const int slot = l0;
         int r = c - pre[slot];
-        const int t = slot >> lg;
+        t = slot >> lg;
         const int ac = slot & (s1 - 1);
         // CRT without 64-bit divisions: every term is below M_t (a residue < m
         // times M_t / m), so the sum is reduced by at most G subtractions
@@ -1539,17 +1608,20 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         }
         const int64_t Mt = d->tup_M[t];
         while (x >= Mt) x -= Mt;
-        int64_t w;
         if (x <= hi) w = x;
         else if (x - Mt >= lo) w = x - Mt;
         else continue;
+        }
 
         // the bin of w in every modulus; the vote counts heavy bins among the
         // moduli outside tuple t (a bin is heavy iff its key >= the block's
         // threshold, i.e. iff it is in the block's heavy set)
         int hh[kMaxK];
         int votes = 0;
-        const int t_lo = t * G, t_hi = t_lo + G;
+        // residue identification: the vote is over the moduli outside tuple t;
+        // phase identification: over all K moduli
+        const int t_lo = (PHASE && phase) ? 0 : t * G, t_hi = (PHASE && phase) ? 0 : t_lo + G;
+        const int need = (PHASE && phase) ? K : K - G;
         auto read_bins = [&](float* er, float* ei) {
 #pragma unroll
             for (int jj = 0; jj < kMaxK; ++jj) {
@@ -1593,8 +1665,30 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
                 }
             }
         }
-        if (2 * votes > K - G) {
+        if (2 * votes > need) {
             if constexpr (use_bm) read_bins(er, ei);
+            if (PHASE && phase) {
+                // one entry per frequency: an earlier modulus whose heavy bin at w
+                // gives w as well produces (and keeps) it
+                bool dup = false;
+#pragma unroll
+                for (int jj = 0; jj < kMaxK; ++jj) {   // compile-time indices: er, ei, hh stay in registers
+                    if (jj < jp && !dup) {
+                        const float2 ev = make_float2(er[jj], ei[jj]);
+                        bool heavy;
+                        if constexpr (use_bm) heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
+                        else heavy = value_key(ev, (uint32_t)hh[jj]) >= sh_thr[jj];
+                        if (heavy) {
+                            const size_t atj = (size_t)Q * d->Moff[jj] + (size_t)b * d->P[jj] +
+                                               ((size_t)(hh[jj] % d->p[jj]) << lg) + (size_t)(hh[jj] & (s1 - 1));
+                            int64_t w2;
+                            dup = phase_frequency(ev, ld2(glb(io.E2) + atj), hh[jj], d->P[jj], d->N, lo, hi, w2) &&
+                                  w2 == w;
+                        }
+                    }
+                }
+                if (dup) continue;
+            }
             const float zr = median_of(er, K);
             const float zi = median_of(ei, K);
             const float m2 = fmaf(zr, zr, zi * zi);
@@ -1809,7 +1903,7 @@ size_t merge_lds_bytes() {
 }
 
 int gather_blocks(const SigDesc& d) { return (d.M + kThreads - 1) / kThreads; }
-int dft_blocks(const SigDesc& d) { return d.K * d.Q; }
+int dft_blocks(const SigDesc& d) { return d.K * d.Q * (1 + d.phase); }
 int identify_blocks(const SigDesc& d) { return d.Q; }
 int merge_blocks(const SigDesc&) { return 1; }
 
@@ -1817,9 +1911,9 @@ int rows_blocks(const SigDesc& d) {
     const int rows_per = std::max(1, kRowElems >> d.log2s1);
     int n = 0;
     for (int j = 0; j < d.K; ++j) n += d.Q * ((d.p[j] + rows_per - 1) / rows_per);
-    return n;
+    return n * (1 + d.phase);
 }
-int cols_blocks(const SigDesc& d) { return d.K * d.Q * (d.s1 / std::min(kColChunk, d.s1)); }
+int cols_blocks(const SigDesc& d) { return d.K * d.Q * (d.s1 / std::min(kColChunk, d.s1)) * (1 + d.phase); }
 int select_blocks(const SigDesc& d) { return d.K * d.Q; }
 
 size_t rows_lds_bytes(const SigDesc& d) {
@@ -1841,7 +1935,9 @@ size_t select_lds_bytes(const SigDesc& d) {
 // reports a size the device cannot hold.
 hipError_t configure_kernels(int max_lds) {
     const void* ks[] = {(const void*)k_dft<8, false>, (const void*)k_dft<16, false>, (const void*)k_dft<0, true>,
-                         (const void*)k_identify<false>, (const void*)k_identify<true>, (const void*)k_merge, (const void*)k_dft_rows,
+                         (const void*)k_identify<false, false>, (const void*)k_identify<true, false>,
+                         (const void*)k_identify<false, true>, (const void*)k_identify<true, true>,
+                         (const void*)k_merge, (const void*)k_dft_rows,
                          (const void*)k_dft_cols, (const void*)k_select};
     for (const void* k : ks) {
         hipFuncAttributes fa;
@@ -1893,10 +1989,16 @@ hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t
 }
 
 hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
-    // lds carries the byte count in its low 32 bits; bit 32 selects the key vote
+    // lds carries the byte count in its low 32 bits; bit 32 selects the key
+    // vote, bit 33 the kernel that also handles phase identification
     const size_t bytes = lds & 0xffffffffu;
-    if (lds >> 32) hipLaunchKernelGGL(k_identify<true>, dim3(blocks), dim3(kThreads), bytes, st, a);
-    else hipLaunchKernelGGL(k_identify<false>, dim3(blocks), dim3(kThreads), bytes, st, a);
+    const dim3 g(blocks), t(kThreads);
+    switch ((int)((lds >> 32) & 3)) {
+        case 0: hipLaunchKernelGGL((k_identify<false, false>), g, t, bytes, st, a); break;
+        case 1: hipLaunchKernelGGL((k_identify<true, false>), g, t, bytes, st, a); break;
+        case 2: hipLaunchKernelGGL((k_identify<false, true>), g, t, bytes, st, a); break;
+        default: hipLaunchKernelGGL((k_identify<true, true>), g, t, bytes, st, a); break;
+    }
     return hipGetLastError();
 }
 

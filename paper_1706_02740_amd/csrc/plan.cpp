@@ -43,6 +43,7 @@ int derive_plan(int64_t N, int32_t s, const sft_params* prm, sft_plan_info* out,
     if (N < 2) { *why = "N must be at least 2"; return SFT_EINVAL; }
     if (N > ((int64_t)1 << 31) - 1) { *why = "N above 2^31 - 1 is not supported"; return SFT_EUNSUPPORTED; }
     if (s < 1 || (int64_t)s > N) { *why = "s must satisfy 1 <= s <= N"; return SFT_EINVAL; }
+    if (p.ident != SFT_IDENT_RESIDUE && p.ident != SFT_IDENT_PHASE) { *why = "unknown identification"; return SFT_EINVAL; }
     const double lnN = log((double)N);
     int32_t kappa;
     double sigma_t, beta, r = 0.0;
@@ -128,6 +129,7 @@ int derive_plan(int64_t N, int32_t s, const sft_params* prm, sft_plan_info* out,
     out->K = K;
     out->T = (int32_t)T;
     out->depth = depth;
+    out->ident = p.ident;
     out->sigma_t = sigma_t;
     out->beta = beta;
     out->c1 = c1;
@@ -161,6 +163,7 @@ void fill_desc(const sft_plan_info& in, SigDesc* d) {
     while (tp < in.T) tp *= 2;
     d->Tpow2 = tp;
     d->depth = in.depth;
+    d->phase = in.ident == SFT_IDENT_PHASE ? 1 : 0;
     d->M = (int32_t)in.M;
     int ac = 256;
     while (ac < 8 * in.s && ac < kAcceptCap) ac *= 2;
@@ -214,6 +217,8 @@ WorkspaceLayout workspace_layout(const sft_plan_info& in) {
     const size_t QM = (size_t)in.Q * (size_t)in.M;
     w.S = align256(QM * 8);
     w.E = align256(QM * 8);
+    w.S2 = in.ident == SFT_IDENT_PHASE ? align256(QM * 8) : 0;
+    w.E2 = w.S2;
     w.H = align256((size_t)in.K * in.Q * in.T * 4);
     w.thr = align256((size_t)in.K * in.Q * 8);
     w.CL = align256((size_t)in.K * in.Q * in.s1 * in.depth * 4);
@@ -221,7 +226,7 @@ WorkspaceLayout workspace_layout(const sft_plan_info& in) {
     w.Rv = align256((size_t)in.Q * in.s * 16);
     w.Rn = align256((size_t)in.Q * 4);
     w.status = 256;
-    w.total = w.S + w.E + w.H + w.thr + w.CL + w.Rw + w.Rv + w.Rn + w.status;
+    w.total = w.S + w.E + w.S2 + w.E2 + w.H + w.thr + w.CL + w.Rw + w.Rv + w.Rn + w.status;
     return w;
 }
 

@@ -38,6 +38,7 @@ struct SigDesc {
     int32_t s, kappa, taps, Q, K, G, s1, log2s1, T, depth, M, Tpow2;
     int32_t accept_cap;     // accepted candidates one band may hold: min(4096, pow2 >= 8 s)
     int32_t vote_bitmap;    // 1: the heavy-bin bitmaps of identify fit the LDS; 0: identify must vote from bin keys
+    int32_t phase;          // 1: phase identification (samples and bins also at the nodes moved one grid step)
     float   inv2sig2;       // 1 / (2 sigma_t^2)
     float   wnorm;          // 1 / (2 pi sigma_t): W(v) = wnorm exp(-v^2 inv2sig2)
     float   gtap[kFastTaps];  // exp(-(i - kappa)^2 inv2sig2), i < taps (taps <= kFastTaps)
@@ -78,6 +79,8 @@ struct IoDesc {
     int32_t* out_n;
     float2* S;        // [Q*M] filtered samples
     float2* E;        // [Q*M] short-DFT bins
+    float2* S2;       // [Q*M] samples at the nodes moved one grid step (phase identification), else null
+    float2* E2;       // [Q*M] their short-DFT bins
     int32_t* H;       // [K*Q*T] heavy bins, ascending Good-Thomas position (for inspection)
     uint64_t* thr;    // [K*Q] selection threshold: a bin is heavy iff its key >= thr
     int32_t* CL;      // [K*Q*s1*depth] per residue class: heaviest heavy bins, -1 padded
@@ -102,7 +105,7 @@ struct BatchArgs {
 
 // Per-signal workspace sizes in bytes (each slice 256-byte aligned).
 struct WorkspaceLayout {
-    size_t S, E, H, thr, CL, Rw, Rv, Rn, status, total;
+    size_t S, E, S2, E2, H, thr, CL, Rw, Rv, Rn, status, total;
 };
 
 // plan.cpp

@@ -43,7 +43,8 @@ CASES = [
     (2 ** 22, 64, {"preset": 2}), (2 ** 20, 50, {"preset": 1}), (2 ** 20, 50, {"preset": 2, "r": 2.0}),
     (2 ** 16, 40, {"s1_mult": 2}), (2 ** 16, 40, {"group": 3}), (2 ** 16, 40, {"heavy_T": 17}),
     (2 ** 16, 40, {"tau": 0.2}), (2 ** 16, 40, {"kappa": 8}), (2 ** 16, 40, {"sigma_t": 1.7}),
-    (65537, 7, {"preset": 1}), (2 ** 30, 64, {}),
+    (65537, 7, {"preset": 1}), (2 ** 30, 64, {}), (2 ** 22, 64, {"ident": 1}),
+    (3001, 5, {"ident": 1, "kappa": 12}),
 ]
 
 
@@ -51,7 +52,7 @@ CASES = [
 def test_library_plan_equals_oracle_plan(N, s, kw):
     lib = sftlib.describe(N, s, **kw)
     orc = oracle.make_plan(N, s, oracle.Params(**kw))
-    for name in ("N", "s", "kappa", "Q", "L", "s1", "G", "K", "T", "preset"):
+    for name in ("N", "s", "kappa", "Q", "L", "s1", "G", "K", "T", "preset", "ident"):
         assert lib[name] == getattr(orc, name), name
     assert lib["primes"] == orc.primes
     assert lib["P"] == orc.P
@@ -63,7 +64,7 @@ def test_library_plan_equals_oracle_plan(N, s, kw):
 
 
 @pytest.mark.parametrize("N,s,kw", [(12, 2, {}), (100, 0, {}), (100, 101, {}), (100, 5, {"tau": 0.5}),
-                                    (30, 2, {"preset": 2, "r": 1.0}), (30, 1, {})])
+                                    (30, 2, {"preset": 2, "r": 1.0}), (30, 1, {}), (100, 5, {"ident": 2})])
 def test_invalid_plans_rejected_alike(N, s, kw):
     with pytest.raises(ValueError):
         oracle.make_plan(N, s, oracle.Params(**kw))
