@@ -83,7 +83,8 @@ def measured_traffic(kernel: str):
     except (KeyError, ValueError, ZeroDivisionError):
         return None
     return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
-            "fetch_scale": f_scale, "write_scale": w_scale}
+            "fetch_scale": f_scale, "write_scale": w_scale,
+            "transforms_per_launch": int(vals.get("transforms_per_launch", "256"))}
 
 
 def uneven_batch(sft, siggen, torch, stream, reps: int = 3) -> dict:
@@ -168,14 +169,14 @@ def serving_runs(sft, siggen, torch, distinct: int = 256, arrivals: int = 1024,
 
 
 def noise_robustness(sft, siggen, torch, stream, trials: int = 100,
-                     snrs=(-20, -10, 0, 10, 20, 30, 40, 50, 60)) -> dict:
+                     snrs=(-20, -10, 0, 10, 20, 30, 40, 50, 60), ident: str = "residue") -> dict:
     """Section 5.4's protocol for this method: N = 2^22, s = 50, unit-magnitude
     random-phase coefficients, complex Gaussian noise at each SNR (dB), 100
     trial signals per level.  Reports the fraction of trials whose recovered
     support is the true one and, over those, the mean of the average L1 error
     (1/s) sum_{w in S} |c_w - z_w|."""
     N, s = 2 ** 22, 50
-    plan = sft.Plan(N, s)
+    plan = sft.Plan(N, s, ident=ident)
     out = {}
     for snr in snrs:
         fs, truth = [], []
@@ -193,9 +194,47 @@ def noise_robustness(sft, siggen, torch, stream, trials: int = 100,
                 errs.append(sum(abs(complex(cv) - tr[int(wv)]) for wv, cv in zip(wg, cg)) / s)
         out[str(snr)] = {"support_rate": ok / trials, "avg_l1_error": float(np.mean(errs)) if errs else None}
         del fs
-    print("[bench] noise robustness: " + ", ".join(f"{k} dB: {v['support_rate']:.2f} / {v['avg_l1_error']}"
-                                                 for k, v in out.items()), file=sys.stderr, flush=True)
-    return {"N": N, "s": s, "trials": trials, "by_snr_db": out}
+    print(f"[bench] noise robustness ({ident}): " +
+          ", ".join(f"{k} dB: {v['support_rate']:.2f} / {v['avg_l1_error']}" for k, v in out.items()),
+          file=sys.stderr, flush=True)
+    return {"N": N, "s": s, "trials": trials, "ident": ident, "by_snr_db": out}
+
+
+def phase_identification(sft, siggen, torch, stream, inputs, steps: int, trials: int = 30,
+                         snrs=(0, 10, 20, 30, 40, 60)) -> dict:
+    """The phase-shift identification on the headline workload: batched
+    throughput over the same resident inputs (twice the samples and short
+    DFTs of the residue identification), then Section 5.4's noise protocol
+    (N = 2^22, s = 50) with `trials` signals per SNR: fraction of trials with
+    the true support and the mean average L1 error over those."""
+    N, s = 2 ** 22, 64
+    plan = sft.Plan(N, s, ident="phase")
+    B = len(inputs)
+    outs = [(torch.empty(s, dtype=torch.int64, device="cuda"), torch.empty(s, dtype=torch.complex64, device="cuda"))
+            for _ in range(B)]
+    counts = torch.empty(B, dtype=torch.int32, device="cuda")
+    sft.execute_many([plan] * B, inputs, outs, counts, stream)
+    torch.cuda.synchronize()
+    sft.profile_reset()
+    sft.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sft.execute_many([plan] * B, inputs, outs, counts, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sft.profile_enable(False)
+    kern = {}
+    for kid, name in sft.KERNEL_NAMES.items():
+        n, ms = sft.profile_read(kid)
+        if n:
+            kern[name] = {"launches": n, "avg_ms": ms / n}
+    rate = B * steps / dt
+    print(f"[bench] phase identification: {1e3 * dt / steps:.3f} ms/step, {rate:.0f} SFT/s", file=sys.stderr,
+          flush=True)
+    del outs
+    noise = noise_robustness(sft, siggen, torch, stream, trials=trials, snrs=snrs, ident="phase")
+    return {"N": N, "s": s, "batch": B, "steps": steps, "sft_per_s": rate, "ms_per_step": 1e3 * dt / steps,
+            "kernels": kern, "noise_robustness": noise}
 
 
 def main():
@@ -212,6 +251,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--no-noise", action="store_true", help="skip the noise-robustness sweep")
+    ap.add_argument("--no-phase", action="store_true", help="skip the phase-identification runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -316,7 +356,9 @@ def main():
     if dom in work and kern[dom]["avg_ms"] > 0:
         byts, flops = work[dom]
         ach = per_kernel[dom]["GBps"]
-        tr = measured_traffic(dom) if tpl[dom] == 64 else None
+        tr = measured_traffic(dom)
+        if tr and tr["transforms_per_launch"] != tpl[dom]:   # counters taken at another batch size
+            tr = None
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None,
                 "traffic_detail": tr,
@@ -366,6 +408,7 @@ def main():
     uneven = None if args.no_uneven else uneven_batch(sft, siggen, torch, stream)
     serving = None if args.no_serve else serving_runs(sft, siggen, torch)
     noise = None if args.no_noise else noise_robustness(sft, siggen, torch, stream)
+    phase = None if args.no_phase else phase_identification(sft, siggen, torch, stream, inputs, max(2, args.steps // 2))
 
     if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
         n = args.calib_copy_mib * 2 ** 20 // 4
@@ -398,6 +441,7 @@ def main():
         "uneven_batch": uneven,
         "serving": serving,
         "noise_robustness": noise,
+        "phase_identification": phase,
     }
     print(json.dumps(out), flush=True)
 
