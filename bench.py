@@ -237,6 +237,39 @@ def phase_identification(sft, siggen, torch, stream, inputs, steps: int, trials:
             "kernels": kern, "noise_robustness": noise}
 
 
+def graph_replay(sft, torch, plans, inputs, steps: int, stream) -> dict:
+    """The headline batch as a prepared batch replayed through its captured
+    hipGraph: SFT/s, and the host time to enqueue one batch (execute_many
+    rebuilds and uploads its descriptor tables on every call; the graph
+    launch does neither)."""
+    B = len(plans)
+    batch = sft.Batch(plans, inputs)
+    batch.graph_launch(stream)   # captures
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.graph_launch(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    host = {}
+    for name, fn in (("execute_many", lambda: sft.execute_many(plans, inputs, batch.outs, batch.counts, stream)),
+                     ("graph_launch", lambda: batch.graph_launch(stream))):
+        ts = []
+        for _ in range(10):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            fn()
+            ts.append(1e6 * (time.perf_counter() - a))
+        torch.cuda.synchronize()
+        host[name] = float(np.median(ts))
+    batch.close()
+    rate = B * steps / dt
+    print(f"[bench] graph replay: {1e3 * dt / steps:.3f} ms/step, {rate:.0f} SFT/s; host enqueue "
+          f"{host['execute_many']:.0f} us (execute_many) vs {host['graph_launch']:.0f} us (graph)",
+          file=sys.stderr, flush=True)
+    return {"sft_per_s": rate, "ms_per_step": 1e3 * dt / steps, "host_enqueue_us": host}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +285,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--no-noise", action="store_true", help="skip the noise-robustness sweep")
     ap.add_argument("--no-phase", action="store_true", help="skip the phase-identification runs")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay run")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -408,6 +442,7 @@ def main():
     uneven = None if args.no_uneven else uneven_batch(sft, siggen, torch, stream)
     serving = None if args.no_serve else serving_runs(sft, siggen, torch)
     noise = None if args.no_noise else noise_robustness(sft, siggen, torch, stream)
+    graph = None if args.no_graph else graph_replay(sft, torch, plans, inputs, args.steps, stream)
     phase = None if args.no_phase else phase_identification(sft, siggen, torch, stream, inputs, max(2, args.steps // 2))
 
     if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
@@ -442,6 +477,7 @@ def main():
         "serving": serving,
         "noise_robustness": noise,
         "phase_identification": phase,
+        "graph_replay": graph,
     }
     print(json.dumps(out), flush=True)
 

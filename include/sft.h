@@ -186,6 +186,32 @@ SFT_API int sft_execute_many(const sft_plan_t* plans, int32_t count, const void*
                      int32_t* out_counts_dev, void* stream);
 
 /*
+ * Prepared batches: the transforms of sft_execute_many with their inputs and
+ * outputs fixed once, for callers that run the same batch shape again and
+ * again (a serving slot, a pipeline stage).  Same computation and results as
+ * sft_execute_many over the same arguments (Algorithm 1 per transform).
+ *
+ * sft_batch_create (host, synchronous): validates the arguments as
+ *   sft_execute_many does, allocates the batch's own workspace and uploads
+ *   its descriptor tables.  The plans must stay alive and the device buffers
+ *   valid while the batch exists; the caller rewrites the contents of the
+ *   input buffers between launches.  out_counts_dev may be NULL.
+ * sft_batch_launch: enqueues the kernel sequence on stream: no allocation,
+ *   no copies, no host synchronisation (so it may itself be captured).
+ * sft_batch_graph_launch: the first call captures that kernel sequence into a
+ *   hipGraph (on a stream of the batch's own) and instantiates it; every call
+ *   launches the graph on stream.  Launches of one batch share its workspace:
+ *   they must not overlap (order them on one stream).
+ * sft_batch_destroy: frees the batch; it must be idle.  NULL is a no-op.
+ */
+typedef struct sft_batch_s* sft_batch_t;
+SFT_API int sft_batch_create(sft_batch_t* out, const sft_plan_t* plans, int32_t count, const void* const* f_dev,
+                             int64_t* const* out_freqs_dev, void* const* out_coeffs_dev, int32_t* out_counts_dev);
+SFT_API int sft_batch_launch(sft_batch_t batch, void* stream);
+SFT_API int sft_batch_graph_launch(sft_batch_t batch, void* stream);
+SFT_API void sft_batch_destroy(sft_batch_t batch);
+
+/*
  * Synchronise with the plan's last sft_execute and return its device-side
  * status flags (0 = fine; bit 0: accepted-candidate list of a band overflowed;
  * bit 1: merge list overflowed).  Returns SFT_EOVERFLOW if any flag is set.

@@ -63,7 +63,8 @@ EXPORTED = [
     "sft_params_default", "sft_plan_describe", "sft_plan_create", "sft_plan_get_info",
     "sft_plan_footprint", "sft_execute", "sft_execute_many", "sft_plan_status",
     "sft_plan_fetch", "sft_plan_destroy", "sft_last_error", "sft_profile_enable",
-    "sft_profile_reset", "sft_profile_read",
+    "sft_profile_reset", "sft_profile_read", "sft_batch_create", "sft_batch_launch",
+    "sft_batch_graph_launch", "sft_batch_destroy",
 ]
 
 
@@ -122,8 +123,14 @@ def load_library():
     lib.sft_profile_enable.argtypes = [c.c_int32]
     lib.sft_profile_reset.argtypes = []
     lib.sft_profile_read.argtypes = [c.c_int32, c.POINTER(c.c_int64), c.POINTER(c.c_double)]
+    lib.sft_batch_create.argtypes = [c.POINTER(vp), c.POINTER(vp), c.c_int32, c.POINTER(vp), c.POINTER(vp),
+                                     c.POINTER(vp), vp]
+    lib.sft_batch_launch.argtypes = [vp, vp]
+    lib.sft_batch_graph_launch.argtypes = [vp, vp]
+    lib.sft_batch_destroy.argtypes = [vp]
+    lib.sft_batch_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("sft_plan_destroy", "sft_last_error"):
+        if name not in ("sft_plan_destroy", "sft_last_error", "sft_batch_destroy"):
             getattr(lib, name).restype = c.c_int
     _lib = lib
     return lib
@@ -283,6 +290,55 @@ def execute_many(plans: Sequence[Plan], fs, outs=None, counts=None, stream=None)
     _check(load_library().sft_execute_many(hp, n, hf, hw, hc, ctypes.c_void_p(counts.data_ptr()),
                                            _stream_handle(stream)))
     return outs, counts
+
+
+class Batch:
+    """A prepared batch (sft_batch_*): the plans, inputs and outputs of an
+    execute_many fixed once; launch() enqueues the kernels only, graph_launch()
+    replays them as a captured hipGraph.  Rewrite the input tensors in place
+    between launches; launches of one batch must not overlap."""
+
+    def __init__(self, plans: Sequence[Plan], fs, outs=None, counts=None):
+        import torch
+        n = len(plans)
+        if n < 1 or len(fs) != n:
+            raise ValueError("plans and fs must be non-empty and of equal length")
+        for p, f in zip(plans, fs):
+            if f.dtype != torch.complex64 or f.dim() != 1 or f.shape[0] != p.N or not f.is_cuda \
+                    or not f.is_contiguous():
+                raise ValueError("every f must be a contiguous complex64 cuda tensor of its plan's length")
+        if outs is None:
+            outs = [(torch.empty(p.s, dtype=torch.int64, device=f.device),
+                     torch.empty(p.s, dtype=torch.complex64, device=f.device)) for p, f in zip(plans, fs)]
+        if counts is None:
+            counts = torch.empty(n, dtype=torch.int32, device=fs[0].device)
+        # the batch holds device pointers: keep the tensors and plans alive with it
+        self.plans, self.fs, self.outs, self.counts = list(plans), list(fs), outs, counts
+        VP = ctypes.c_void_p * n
+        self._h = ctypes.c_void_p()
+        _check(load_library().sft_batch_create(
+            ctypes.byref(self._h), VP(*[p.handle.value for p in plans]), n, VP(*[f.data_ptr() for f in fs]),
+            VP(*[o[0].data_ptr() for o in outs]), VP(*[o[1].data_ptr() for o in outs]),
+            ctypes.c_void_p(counts.data_ptr())))
+
+    def launch(self, stream=None):
+        _check(load_library().sft_batch_launch(self._h, _stream_handle(stream)))
+        return self.outs, self.counts
+
+    def graph_launch(self, stream=None):
+        _check(load_library().sft_batch_graph_launch(self._h, _stream_handle(stream)))
+        return self.outs, self.counts
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().sft_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True):

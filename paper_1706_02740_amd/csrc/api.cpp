@@ -383,18 +383,111 @@ LaunchFn launcher(int k) {
 // Enqueue the pipeline.  prefix[k] is the device prefix table of kernel k
 // (batch of several plans), bps[k] the blocks per transform of a one-plan
 // batch; both null for a single transform.
+// timing: per-kernel HIP events when profiling is on (off while a graph is
+// captured).
 int enqueue(BatchArgs a, const int blocks[SFT_KERNEL_COUNT], const size_t lds[SFT_KERNEL_COUNT],
-            const int32_t* const prefix[SFT_KERNEL_COUNT], hipStream_t st, const int* bps) {
+            const int32_t* const prefix[SFT_KERNEL_COUNT], hipStream_t st, const int* bps, bool timing = true) {
     for (int o = 0; o < SFT_KERNEL_COUNT; ++o) {
         const int k = kOrder[o];
         if (blocks[k] <= 0) continue;
         a.prefix = prefix ? prefix[k] : nullptr;
         a.bps = bps ? bps[k] : 0;
         LaunchFn fn = launcher(k);
-        const hipError_t e = timed(k, st, [&] { return fn(a, blocks[k], lds[k], st); });
+        const hipError_t e = timing ? timed(k, st, [&] { return fn(a, blocks[k], lds[k], st); })
+                                    : fn(a, blocks[k], lds[k], st);
         if (e != hipSuccess) return hip_fail(e, kNames[k]);
     }
     return SFT_OK;
+}
+
+// ------------------------------------------------------------ batches ----
+// A batch of transforms: every transform's workspace slice, the launch
+// parameters merged over the plans, and the descriptor tables
+// ([count] descriptor pointers | [count] IoDesc | one [count+1] block prefix
+// per kernel).
+struct BatchShape {
+    std::vector<size_t> wsoff;
+    size_t ws_total = 0;
+    size_t lds[SFT_KERNEL_COUNT] = {};
+    size_t m_desc = 0, m_io = 0, m_pre = 0, meta_total = 0;
+    bool one_plan = true;
+};
+
+int batch_shape(const sft_plan_t* plans, int32_t count, const void* const* f_dev, int64_t* const* out_freqs_dev,
+                void* const* out_coeffs_dev, int dev, BatchShape& B) {
+    if (!plans || !f_dev || !out_freqs_dev || !out_coeffs_dev) return fail(SFT_EINVAL, "NULL argument");
+    B.wsoff.assign(count, 0);
+    for (int i = 0; i < count; ++i) {
+        const sft_plan_s* p = plans[i];
+        if (!p || !f_dev[i] || !out_freqs_dev[i] || !out_coeffs_dev[i]) return fail(SFT_EINVAL, "NULL entry");
+        if (p->device != dev) return fail(SFT_EINVAL, "plan belongs to another device");
+        B.one_plan &= p == plans[0];
+        B.wsoff[i] = B.ws_total;
+        B.ws_total += p->wl.total;
+        for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
+            if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes); identify's flags: union
+                const size_t hi = k == SFT_KERNEL_IDENTIFY ? (p->lds[k] >> 32) | (B.lds[k] >> 32)
+                                                           : std::max(p->lds[k] >> 32, B.lds[k] >> 32);
+                const size_t lo = std::max(p->lds[k] & 0xffffffffu, B.lds[k] & 0xffffffffu);
+                B.lds[k] = (hi << 32) | lo;
+            }
+        // one compile-time tap count when every transform shares it, else the generic kernel
+        if (i == 0) B.lds[SFT_KERNEL_GATHER] = p->lds[SFT_KERNEL_GATHER];
+        else if (B.lds[SFT_KERNEL_GATHER] != p->lds[SFT_KERNEL_GATHER]) B.lds[SFT_KERNEL_GATHER] = 0;
+    }
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    B.m_desc = al(sizeof(void*) * count);
+    B.m_io = al(sizeof(IoDesc) * count);
+    B.m_pre = al(sizeof(int32_t) * (count + 1));
+    B.meta_total = B.m_desc + B.m_io + SFT_KERNEL_COUNT * B.m_pre;
+    return SFT_OK;
+}
+
+// The host image of the descriptor tables (hs, meta_total bytes) for the
+// workspace at ws; blocks receives the grid size of every kernel.
+void batch_tables(const BatchShape& B, const sft_plan_t* plans, int32_t count, const void* const* f_dev,
+                  int64_t* const* out_freqs_dev, void* const* out_coeffs_dev, int32_t* out_counts_dev, char* ws,
+                  char* hs, int blocks[SFT_KERNEL_COUNT]) {
+    const SigDesc** hdesc = reinterpret_cast<const SigDesc**>(hs);
+    IoDesc* hio = reinterpret_cast<IoDesc*>(hs + B.m_desc);
+    int32_t* hpre[SFT_KERNEL_COUNT];
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
+        hpre[k] = reinterpret_cast<int32_t*>(hs + B.m_desc + B.m_io + k * B.m_pre);
+        blocks[k] = 0;
+    }
+    for (int i = 0; i < count; ++i) {
+        const sft_plan_s* p = plans[i];
+        hdesc[i] = p->ddesc;
+        IoDesc io = carve(ws + B.wsoff[i], p->wl);
+        io.f = static_cast<const float2*>(f_dev[i]);
+        io.out_w = out_freqs_dev[i];
+        io.out_c = static_cast<float2*>(out_coeffs_dev[i]);
+        io.out_n = out_counts_dev ? out_counts_dev + i : nullptr;
+        hio[i] = io;
+        for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
+            hpre[k][i] = blocks[k];
+            blocks[k] += p->blocks[k];
+        }
+    }
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) hpre[k][count] = blocks[k];
+}
+
+// Enqueue a batch whose descriptor tables are on the device at dm.
+int enqueue_batch(const BatchShape& B, const sft_plan_t* plans, int32_t count, char* dm,
+                  const int blocks[SFT_KERNEL_COUNT], hipStream_t st, bool timing) {
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.io_many = reinterpret_cast<const IoDesc*>(dm + B.m_desc);
+    a.nsig = count;
+    if (B.one_plan) {   // blocks follow from blockIdx by a division; one descriptor
+        a.desc_one = plans[0]->ddesc;
+        return enqueue(a, blocks, B.lds, nullptr, st, plans[0]->blocks, timing);
+    }
+    a.descs_many = reinterpret_cast<const SigDesc* const*>(dm);
+    const int32_t* dpre[SFT_KERNEL_COUNT];
+    for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
+        dpre[k] = reinterpret_cast<const int32_t*>(dm + B.m_desc + B.m_io + k * B.m_pre);
+    return enqueue(a, blocks, B.lds, dpre, st, nullptr, timing);
 }
 
 // ----------------------------------------------------- batch arenas ----
@@ -473,100 +566,123 @@ int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* 
                      void* stream) {
     if (count < 0) return fail(SFT_EINVAL, "count must be >= 0");
     if (count == 0) return SFT_OK;
-    if (!plans || !f_dev || !out_freqs_dev || !out_coeffs_dev) return fail(SFT_EINVAL, "NULL argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    // sizes
-    std::vector<size_t> wsoff(count);
-    size_t ws_total = 0;
-    size_t lds[SFT_KERNEL_COUNT] = {};
-    for (int i = 0; i < count; ++i) {
-        const sft_plan_s* p = plans[i];
-        if (!p || !f_dev[i] || !out_freqs_dev[i] || !out_coeffs_dev[i]) return fail(SFT_EINVAL, "NULL entry");
-        if (p->device != dev) return fail(SFT_EINVAL, "plan belongs to another device");
-        wsoff[i] = ws_total;
-        ws_total += p->wl.total;
-        for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
-            if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes); identify's flags: union
-                const size_t hi = k == SFT_KERNEL_IDENTIFY ? (p->lds[k] >> 32) | (lds[k] >> 32)
-                                                           : std::max(p->lds[k] >> 32, lds[k] >> 32);
-                const size_t lo = std::max(p->lds[k] & 0xffffffffu, lds[k] & 0xffffffffu);
-                lds[k] = (hi << 32) | lo;
-            }
-        // one compile-time tap count when every transform shares it, else the generic kernel
-        if (i == 0) lds[SFT_KERNEL_GATHER] = p->lds[SFT_KERNEL_GATHER];
-        else if (lds[SFT_KERNEL_GATHER] != p->lds[SFT_KERNEL_GATHER]) lds[SFT_KERNEL_GATHER] = 0;
-    }
-    // meta layout: [count] desc pointers | [count] IoDesc | SFT_KERNEL_COUNT x [count+1] prefixes
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t m_desc = al(sizeof(void*) * count);
-    const size_t m_io = al(sizeof(IoDesc) * count);
-    const size_t m_pre = al(sizeof(int32_t) * (count + 1));
-    const size_t meta_total = m_desc + m_io + SFT_KERNEL_COUNT * m_pre;
+    BatchShape B;
+    const int rc = batch_shape(plans, count, f_dev, out_freqs_dev, out_coeffs_dev, dev, B);
+    if (rc != SFT_OK) return rc;
 
     Arena* ar = arena_for(dev, st);
     if (ar->staged) HIP_TRY(hipEventSynchronize(ar->staged), "hipEventSynchronize");
-    if (ar->ws_bytes < ws_total || ar->meta_bytes < meta_total) {
+    if (ar->ws_bytes < B.ws_total || ar->meta_bytes < B.meta_total) {
         HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-        if (ar->ws_bytes < ws_total) {
+        if (ar->ws_bytes < B.ws_total) {
             if (ar->ws) (void)hipFree(ar->ws);
             ar->ws = nullptr;
             ar->ws_bytes = 0;
-            if (hipMalloc(&ar->ws, ws_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch workspace) failed");
-            ar->ws_bytes = ws_total;
+            if (hipMalloc(&ar->ws, B.ws_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch workspace) failed");
+            ar->ws_bytes = B.ws_total;
         }
-        if (ar->meta_bytes < meta_total) {
+        if (ar->meta_bytes < B.meta_total) {
             if (ar->meta) (void)hipFree(ar->meta);
             if (ar->staging) (void)hipHostFree(ar->staging);
             ar->meta = nullptr;
             ar->staging = nullptr;
             ar->meta_bytes = 0;
-            if (hipMalloc(&ar->meta, meta_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch meta) failed");
-            if (hipHostMalloc(&ar->staging, meta_total, hipHostMallocDefault) != hipSuccess)
+            if (hipMalloc(&ar->meta, B.meta_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch meta) failed");
+            if (hipHostMalloc(&ar->staging, B.meta_total, hipHostMallocDefault) != hipSuccess)
                 return fail(SFT_ENOMEM, "hipHostMalloc(batch staging) failed");
-            ar->meta_bytes = meta_total;
+            ar->meta_bytes = B.meta_total;
         }
         if (!ar->staged) HIP_TRY(hipEventCreateWithFlags(&ar->staged, hipEventDisableTiming), "hipEventCreate");
     }
-    char* hs = static_cast<char*>(ar->staging);
-    const SigDesc** hdesc = reinterpret_cast<const SigDesc**>(hs);
-    IoDesc* hio = reinterpret_cast<IoDesc*>(hs + m_desc);
-    int32_t* hpre[SFT_KERNEL_COUNT];
-    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) hpre[k] = reinterpret_cast<int32_t*>(hs + m_desc + m_io + k * m_pre);
-    int blocks[SFT_KERNEL_COUNT] = {};
-    for (int i = 0; i < count; ++i) {
-        const sft_plan_s* p = plans[i];
-        hdesc[i] = p->ddesc;
-        IoDesc io = carve(static_cast<char*>(ar->ws) + wsoff[i], p->wl);
-        io.f = static_cast<const float2*>(f_dev[i]);
-        io.out_w = out_freqs_dev[i];
-        io.out_c = static_cast<float2*>(out_coeffs_dev[i]);
-        io.out_n = out_counts_dev ? out_counts_dev + i : nullptr;
-        hio[i] = io;
-        for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
-            hpre[k][i] = blocks[k];
-            blocks[k] += p->blocks[k];
-        }
-    }
-    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) hpre[k][count] = blocks[k];
-    HIP_TRY(hipMemcpyAsync(ar->meta, ar->staging, meta_total, hipMemcpyHostToDevice, st), "hipMemcpyAsync(meta)");
+    int blocks[SFT_KERNEL_COUNT];
+    batch_tables(B, plans, count, f_dev, out_freqs_dev, out_coeffs_dev, out_counts_dev, static_cast<char*>(ar->ws),
+                 static_cast<char*>(ar->staging), blocks);
+    HIP_TRY(hipMemcpyAsync(ar->meta, ar->staging, B.meta_total, hipMemcpyHostToDevice, st), "hipMemcpyAsync(meta)");
     HIP_TRY(hipEventRecord(ar->staged, st), "hipEventRecord");
-    char* dm = static_cast<char*>(ar->meta);
-    BatchArgs a;
-    memset(&a, 0, sizeof(a));
-    a.io_many = reinterpret_cast<const IoDesc*>(dm + m_desc);
-    a.nsig = count;
-    bool one_plan = true;
-    for (int i = 1; i < count; ++i) one_plan &= plans[i] == plans[0];
-    if (one_plan) {   // blocks follow from blockIdx by a division; one descriptor
-        a.desc_one = plans[0]->ddesc;
-        return enqueue(a, blocks, lds, nullptr, st, plans[0]->blocks);
+    return enqueue_batch(B, plans, count, static_cast<char*>(ar->meta), blocks, st, true);
+}
+
+// --------------------------------------------------- prepared batches ----
+struct sft_batch_s {
+    int32_t count = 0;
+    std::vector<sft_plan_t> plans;
+    BatchShape shape;
+    int blocks[SFT_KERNEL_COUNT] = {};
+    void* ws = nullptr;
+    void* meta = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;   // stream of the last launch
+};
+
+void sft_batch_destroy(sft_batch_t b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->last);   // its memory is freed below
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->meta) (void)hipFree(b->meta);
+    if (b->ws) (void)hipFree(b->ws);
+    delete b;
+}
+
+int sft_batch_create(sft_batch_t* out, const sft_plan_t* plans, int32_t count, const void* const* f_dev,
+                     int64_t* const* out_freqs_dev, void* const* out_coeffs_dev, int32_t* out_counts_dev) {
+    if (!out) return fail(SFT_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (count < 1) return fail(SFT_EINVAL, "count must be >= 1");
+    if (!plans) return fail(SFT_EINVAL, "NULL argument");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    sft_batch_s* b = new sft_batch_s();
+    b->count = count;
+    b->plans.assign(plans, plans + count);
+    int rc = batch_shape(plans, count, f_dev, out_freqs_dev, out_coeffs_dev, dev, b->shape);
+    if (rc != SFT_OK) { sft_batch_destroy(b); return rc; }
+    if (hipMalloc(&b->ws, b->shape.ws_total) != hipSuccess || hipMalloc(&b->meta, b->shape.meta_total) != hipSuccess) {
+        sft_batch_destroy(b);
+        return fail(SFT_ENOMEM, "hipMalloc(batch) failed");
     }
-    a.descs_many = reinterpret_cast<const SigDesc* const*>(dm);
-    const int32_t* dpre[SFT_KERNEL_COUNT];
-    for (int k = 0; k < SFT_KERNEL_COUNT; ++k) dpre[k] = reinterpret_cast<const int32_t*>(dm + m_desc + m_io + k * m_pre);
-    return enqueue(a, blocks, lds, dpre, st, nullptr);
+    std::vector<char> hs(b->shape.meta_total, 0);
+    batch_tables(b->shape, plans, count, f_dev, out_freqs_dev, out_coeffs_dev, out_counts_dev,
+                 static_cast<char*>(b->ws), hs.data(), b->blocks);
+    const hipError_t e = hipMemcpy(b->meta, hs.data(), b->shape.meta_total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { sft_batch_destroy(b); return hip_fail(e, "hipMemcpy(batch tables)"); }
+    *out = b;
+    return SFT_OK;
+}
+
+int sft_batch_launch(sft_batch_t b, void* stream) {
+    if (!b) return fail(SFT_EINVAL, "NULL batch");
+    b->last = static_cast<hipStream_t>(stream);
+    return enqueue_batch(b->shape, b->plans.data(), b->count, static_cast<char*>(b->meta), b->blocks,
+                         static_cast<hipStream_t>(stream), true);
+}
+
+int sft_batch_graph_launch(sft_batch_t b, void* stream) {
+    if (!b) return fail(SFT_EINVAL, "NULL batch");
+    if (!b->exec) {   // capture the launch sequence once, on a stream of the batch's own
+        if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
+        HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        const int rc = enqueue_batch(b->shape, b->plans.data(), b->count, static_cast<char*>(b->meta), b->blocks,
+                                     b->capture, false);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->capture, &g);
+        if (rc != SFT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+    b->last = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+    return SFT_OK;
 }
 
 int sft_plan_status(sft_plan_t plan, int32_t* flags) {
