@@ -108,6 +108,16 @@ def uneven_batch(sft, siggen, torch, stream, reps: int = 3) -> dict:
         sft.execute_many(pl, fs, outs, counts, stream)
     torch.cuda.synchronize()
     batched_s = (time.perf_counter() - t0) / reps
+    sft.profile_reset()   # one more batch with per-kernel events
+    sft.profile_enable(True)
+    sft.execute_many(pl, fs, outs, counts, stream)
+    torch.cuda.synchronize()
+    sft.profile_enable(False)
+    kern = {}
+    for kid, name in sft.KERNEL_NAMES.items():
+        n, ms = sft.profile_read(kid)
+        if n:
+            kern[name] = ms / n
     pouts = [p.outputs() for p in pl]
     t0 = time.perf_counter()
     for p, f, o in zip(pl, fs, pouts):
@@ -120,7 +130,7 @@ def uneven_batch(sft, siggen, torch, stream, reps: int = 3) -> dict:
           flush=True)
     return {"signals": len(pl), "plans": len(plans), "batched_sft_per_s": len(pl) / batched_s,
             "plain_sft_per_s": len(pl) / plain_s, "batch_ms": batched_s * 1e3, "plain_ms": plain_s * 1e3,
-            "filtered_samples": samples, "outputs_equal": bool(equal)}
+            "filtered_samples": samples, "outputs_equal": bool(equal), "kernel_ms": kern}
 
 
 def serving_runs(sft, siggen, torch, distinct: int = 256, arrivals: int = 1024,

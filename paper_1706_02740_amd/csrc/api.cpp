@@ -168,7 +168,10 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     } else {
         pl->lds[SFT_KERNEL_DFT_ROWS] = rows_lds_bytes(d);
         pl->lds[SFT_KERNEL_DFT_COLS] = cols_lds_bytes(d);
-        pl->lds[SFT_KERNEL_SELECT] = select_lds_bytes(d);
+        // low 32 bits: the selection that reads E in every pass; above: the
+        // one with the block's keys in LDS, 0 when they do not fit
+        const size_t kbytes = select_lds_bytes(d, true);
+        pl->lds[SFT_KERNEL_SELECT] = select_lds_bytes(d, false) | ((kbytes <= lds_cap ? kbytes : 0) << 32);
         pl->blocks[SFT_KERNEL_DFT_ROWS] = rows_blocks(d);
         pl->blocks[SFT_KERNEL_DFT_COLS] = cols_blocks(d);
         pl->blocks[SFT_KERNEL_SELECT] = select_blocks(d);
@@ -409,6 +412,7 @@ struct BatchShape {
     std::vector<size_t> wsoff;
     size_t ws_total = 0;
     size_t lds[SFT_KERNEL_COUNT] = {};
+    bool used[SFT_KERNEL_COUNT] = {};   // some plan of the batch launches kernel k
     size_t m_desc = 0, m_io = 0, m_pre = 0, meta_total = 0;
     bool one_plan = true;
 };
@@ -425,9 +429,14 @@ int batch_shape(const sft_plan_t* plans, int32_t count, const void* const* f_dev
         B.wsoff[i] = B.ws_total;
         B.ws_total += p->wl.total;
         for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
-            if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes); identify's flags: union
-                const size_t hi = k == SFT_KERNEL_IDENTIFY ? (p->lds[k] >> 32) | (B.lds[k] >> 32)
-                                                           : std::max(p->lds[k] >> 32, B.lds[k] >> 32);
+            if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes); identify's flags: union;
+                                            // the selection's LDS-key bytes: 0 if any plan has 0
+                if (p->blocks[k] == 0) continue;   // the plan does not use kernel k
+                const size_t ph = p->lds[k] >> 32, bh = B.lds[k] >> 32;
+                const size_t hi = k == SFT_KERNEL_IDENTIFY ? (ph | bh)
+                                  : k == SFT_KERNEL_SELECT ? (!B.used[k] ? ph : (ph && bh ? std::max(ph, bh) : 0))
+                                                           : std::max(ph, bh);
+                B.used[k] = true;
                 const size_t lo = std::max(p->lds[k] & 0xffffffffu, B.lds[k] & 0xffffffffu);
                 B.lds[k] = (hi << 32) | lo;
             }

@@ -1354,8 +1354,12 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     dft_cols_lds<kThreads>(tile, C, C, p, trig, E + c0, s1, 1.0f / (float)P);
 }
 
-// Split path, selection: one workgroup per (modulus j, band b), E in global memory.
-__global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
+// Split path, selection: one workgroup per (modulus j, band b), E in global
+// memory.  LDSKEYS: the |E|^2 bits of the block are read once into LDS and
+// every pass reads them there (blocks whose keys fit the LDS); otherwise each
+// pass reads E.  The keys and the outputs are the same either way.
+template <int NT, bool LDSKEYS>
+__global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
     const CONSTANT SigDesc* d = desc_of(a, at.sig);
@@ -1371,20 +1375,47 @@ __global__ void __launch_bounds__(kThreads) k_select(BatchArgs a) {
     int32_t* part = hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [2 T]
     int32_t* cl = reinterpret_cast<int32_t*>(hk + 2 * d->T);   // [s1 depth]
+    uint32_t* keys = reinterpret_cast<uint32_t*>(cl + ((s1 * d->depth + 3) & ~3));   // [P] (LDSKEYS)
     const GLOBAL float2* __restrict__ E = glb(io.E) + (size_t)Q * d->Moff[j] + (size_t)b * P;
     const uint32_t cA = (uint32_t)p * (uint32_t)d->pinv_s1[j];
     const uint32_t cB = (uint32_t)s1 * (uint32_t)d->s1inv_p[j];
-    auto kf = [&](int i) { return value_key(ld2(E + i), pfa_bin(i, lg, s1, (uint32_t)P, cA, cB)); };
+    if constexpr (LDSKEYS) {
+        constexpr int U = 8;   // loads of a thread in flight at once
+        for (int i0 = (int)threadIdx.x; i0 < P; i0 += U * NT) {
+            float2 ev[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * NT;
+                ev[u] = i < P ? ld2(E + i) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * NT;
+                if (i < P) keys[i] = __float_as_uint(fmaf(ev[u].x, ev[u].x, ev[u].y * ev[u].y));
+            }
+        }
+        __syncthreads();
+    }
+    auto kf = [&](int i) {
+        const uint32_t bin = pfa_bin(i, lg, s1, (uint32_t)P, cA, cB);
+        if constexpr (LDSKEYS) return ((uint64_t)keys[i] << 32) | (uint64_t)(0xffffffffu - bin);
+        else return value_key(ld2(E + i), bin);
+    };
     auto each = [&](auto f) {
-        for (int i = (int)threadIdx.x; i < P; i += kThreads) {
-            const uint64_t k = kf(i);
-            f((uint32_t)(k >> 32), [k] { return k; });
+        for (int i = (int)threadIdx.x; i < P; i += NT) {
+            if constexpr (LDSKEYS) {
+                const uint32_t h = keys[i];
+                f(h, [&] { return kf(i); });
+            } else {
+                const uint64_t k = kf(i);
+                f((uint32_t)(k >> 32), [k] { return k; });
+            }
         }
     };
-    const uint64_t thr = kth_largest<kThreads>(each, P, d->T, hist, part);
+    const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<kThreads>(kf, P, d->T, s1, d->depth, thr, hk, hist, part, cl, glb(io.H) + blk * d->T,
-                         glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
+    emit_heavy<NT>(kf, P, d->T, s1, d->depth, thr, hk, hist, part, cl, glb(io.H) + blk * d->T,
+                   glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
 }
 
 // ---------------------------------------------------------- k_identify ----
@@ -1926,8 +1957,11 @@ size_t cols_lds_bytes(const SigDesc& d) {
     const size_t h = (size_t)(pmax - 1) / 2;
     return (size_t)pmax * std::min(kColChunk, d.s1) * 8 + h * h * 8 + 64;
 }
-size_t select_lds_bytes(const SigDesc& d) {
-    return kSelBins * 4 + 64 + (size_t)d.T * 16 + (size_t)d.s1 * d.depth * 4 + 64;
+size_t select_lds_bytes(const SigDesc& d, bool lds_keys) {
+    int32_t Pmax = 0;
+    for (int j = 0; j < d.K; ++j) Pmax = d.P[j] > Pmax ? d.P[j] : Pmax;
+    return kSelBins * 4 + 64 + (size_t)d.T * 16 + (((size_t)d.s1 * d.depth + 3) & ~(size_t)3) * 4 +
+           (lds_keys ? (size_t)Pmax * 4 : 0) + 64;
 }
 
 // Dynamic LDS above 64 KiB: raise each kernel's limit where the runtime asks
@@ -1938,7 +1972,8 @@ hipError_t configure_kernels(int max_lds) {
                          (const void*)k_identify<false, false>, (const void*)k_identify<true, false>,
                          (const void*)k_identify<false, true>, (const void*)k_identify<true, true>,
                          (const void*)k_merge, (const void*)k_dft_rows,
-                         (const void*)k_dft_cols, (const void*)k_select};
+                         (const void*)k_dft_cols, (const void*)k_select<kThreads, false>,
+                         (const void*)k_select<kSelLdsThreads, true>};
     for (const void* k : ks) {
         hipFuncAttributes fa;
         int static_lds = 0;
@@ -1984,7 +2019,16 @@ hipError_t launch_dft_cols(const BatchArgs& a, int blocks, size_t lds, hipStream
 }
 
 hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(k_select, dim3(blocks), dim3(kThreads), lds, st, a);
+    // lds: the byte count of the kernel that reads E in every pass (low 32
+    // bits) and of the one holding the keys in LDS (above; 0 if some block's
+    // keys do not fit).  The LDS-key kernel runs one workgroup per CU: it is
+    // taken when the launch has at most one block per CU, where the latency
+    // of a block decides; larger launches keep many workgroups per CU.
+    const size_t bytes = lds & 0xffffffffu, kbytes = lds >> 32;
+    if (kbytes && blocks <= kSelLdsMaxBlocks)
+        hipLaunchKernelGGL((k_select<kSelLdsThreads, true>), dim3(blocks), dim3(kSelLdsThreads), kbytes, st, a);
+    else
+        hipLaunchKernelGGL((k_select<kThreads, false>), dim3(blocks), dim3(kThreads), bytes, st, a);
     return hipGetLastError();
 }
 

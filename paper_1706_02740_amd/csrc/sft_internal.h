@@ -23,6 +23,8 @@ constexpr int kSelBins = 1024;         // buckets of one radix-select pass (10-b
 constexpr int kMxSteps = 8;            // K-steps (4 values of n each) of the matrix-core p-point step: h <= 32
 constexpr int kMxTiles = 2;            // M-tiles (16 values of k each): h + 1 <= 32
 constexpr int kDftKBMax = 16;          // p-point output pairs per thread in the in-LDS short-DFT kernel
+constexpr int kSelLdsThreads = 1024;   // workgroup size of the split path's selection with its keys in LDS
+constexpr int kSelLdsMaxBlocks = 256;  // launches up to this many selection blocks (one per CU) take it
 
 // Status bits written by the device.
 constexpr int kStatusAcceptOverflow = 1;
@@ -134,7 +136,7 @@ int cols_blocks(const SigDesc& d);
 int select_blocks(const SigDesc& d);
 size_t rows_lds_bytes(const SigDesc& d);
 size_t cols_lds_bytes(const SigDesc& d);
-size_t select_lds_bytes(const SigDesc& d);
+size_t select_lds_bytes(const SigDesc& d, bool lds_keys);   // with the block's keys held in LDS or not
 hipError_t launch_dft_rows(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_dft_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_dft_cols(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
