@@ -280,6 +280,36 @@ def graph_replay(sft, torch, plans, inputs, steps: int, stream) -> dict:
     return {"sft_per_s": rate, "ms_per_step": 1e3 * dt / steps, "host_enqueue_us": host}
 
 
+def tuning_sweep(sft, torch, batch: int = 64,
+                 shapes=((2 ** 22, 16), (2 ** 22, 32), (2 ** 22, 64), (2 ** 22, 128), (2 ** 20, 100),
+                         (2 ** 24, 128))) -> dict:
+    """The short-DFT path tuner on representative shapes (a fresh cache, so
+    every path is measured): ms per transform of each path the library
+    accepts, the tuner's choice, and the fixed rule's choice (dft_path 0)."""
+    import tempfile
+
+    from paper_1706_02740_amd import tune
+    out = {}
+    with tempfile.TemporaryDirectory() as tmp:
+        cache = tune.Cache(os.path.join(tmp, "tune.json"))
+        for N, s in shapes:
+            path = tune.best_dft_path(N, s, batch=batch, cache=cache)
+            entry = next(v for k, v in cache.data.items() if f"N={N}|s={s}|" in k)
+            # the fixed rule: matrix cores in LDS if they cover the plan, else VALU in LDS if it fits, else split
+            rule = 2
+            for cand in (3, 1):
+                try:
+                    sft.Plan(N, s, dft_path=cand)
+                except sft.SftError:
+                    continue
+                rule = cand
+                break
+            out[f"N={N},s={s}"] = {"tuned": path, "rule": rule, "ms_per_transform": entry["ms_per_transform"]}
+    print("[bench] tuning: " + "; ".join(f"{k}: {v['tuned']} {v['ms_per_transform']}" for k, v in out.items()),
+          file=sys.stderr, flush=True)
+    return {"batch": batch, "shapes": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +326,7 @@ def main():
     ap.add_argument("--no-noise", action="store_true", help="skip the noise-robustness sweep")
     ap.add_argument("--no-phase", action="store_true", help="skip the phase-identification runs")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay run")
+    ap.add_argument("--no-tune", action="store_true", help="skip the short-DFT path tuning sweep")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -453,6 +484,7 @@ def main():
     serving = None if args.no_serve else serving_runs(sft, siggen, torch)
     noise = None if args.no_noise else noise_robustness(sft, siggen, torch, stream)
     graph = None if args.no_graph else graph_replay(sft, torch, plans, inputs, args.steps, stream)
+    tuning = None if args.no_tune else tuning_sweep(sft, torch)
     phase = None if args.no_phase else phase_identification(sft, siggen, torch, stream, inputs, max(2, args.steps // 2))
 
     if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
@@ -488,6 +520,7 @@ def main():
         "noise_robustness": noise,
         "phase_identification": phase,
         "graph_replay": graph,
+        "tuning": tuning,
     }
     print(json.dumps(out), flush=True)
 
