@@ -295,9 +295,10 @@ def tuning_sweep(sft, torch, batch: int = 64,
         for N, s in shapes:
             path = tune.best_dft_path(N, s, batch=batch, cache=cache)
             entry = next(v for k, v in cache.data.items() if f"N={N}|s={s}|" in k)
-            # the fixed rule: matrix cores in LDS if they cover the plan, else VALU in LDS if it fits, else split
+            # the fixed rule: matrix cores in LDS if they cover the plan, else VALU in LDS if it fits,
+            # else split with matrix-core columns if they cover it, else split
             rule = 2
-            for cand in (3, 1):
+            for cand in (3, 1, 4):
                 try:
                     sft.Plan(N, s, dft_path=cand)
                 except sft.SftError:

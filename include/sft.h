@@ -78,8 +78,11 @@ extern "C" {
  * short-DFT kernels: 0 = automatic (a whole block in LDS with the p-point
  * step on the matrix cores when s1 is 64 or 128 and every (p_j - 1)/2 < 32,
  * else in LDS on the vector ALUs when it fits, else the split path),
- * 1 = in LDS on the vector ALUs, 2 = split, 3 = in LDS on the matrix cores.
- * Paths 1 and 2 give bitwise equal results; path 3 sums in another order.
+ * 1 = in LDS on the vector ALUs, 2 = split, 3 = in LDS on the matrix cores,
+ * 4 = split with the p-point step on the matrix cores (s1 >= 64, every
+ * (p_j - 1)/2 <= 47); automatic takes 4 for plans it would split when it
+ * covers them.  Paths 1 and 2 give bitwise equal results, and so do paths 3
+ * and 4; the matrix-core paths sum the p-point step in another order.
  * ident chooses the identification (SFT_IDENT_*).  SFT_IDENT_PHASE is the
  * phase-shift family that Section 5 pairs with CLW-DSFT (whose inner algorithm
  * the paper does not print): the filtered samples are also taken at every node
@@ -262,7 +265,8 @@ SFT_API const char* sft_last_error(void);
 #define SFT_KERNEL_DFT_COLS 5   /* split path: p-point column DFTs */
 #define SFT_KERNEL_SELECT   6   /* split path: heavy-bin selection from global memory */
 #define SFT_KERNEL_DFT_MX   7   /* as SFT_KERNEL_DFT, the p-point step on the matrix cores */
-#define SFT_KERNEL_COUNT    8
+#define SFT_KERNEL_DFT_COLS_MX 8   /* as SFT_KERNEL_DFT_COLS, on the matrix cores */
+#define SFT_KERNEL_COUNT    9
 SFT_API int sft_profile_enable(int32_t on);
 SFT_API int sft_profile_reset(void);
 SFT_API int sft_profile_read(int32_t kernel, int64_t* launches, double* total_ms);

@@ -53,9 +53,10 @@ KERNEL_DFT_ROWS = 4
 KERNEL_DFT_COLS = 5
 KERNEL_SELECT = 6
 KERNEL_DFT_MX = 7
+KERNEL_DFT_COLS_MX = 8
 KERNEL_NAMES = {KERNEL_GATHER: "k_gather", KERNEL_DFT: "k_dft", KERNEL_IDENTIFY: "k_identify",
                 KERNEL_MERGE: "k_merge", KERNEL_DFT_ROWS: "k_dft_rows", KERNEL_DFT_COLS: "k_dft_cols",
-                KERNEL_SELECT: "k_select", KERNEL_DFT_MX: "k_dft_mx"}
+                KERNEL_SELECT: "k_select", KERNEL_DFT_MX: "k_dft_mx", KERNEL_DFT_COLS_MX: "k_dft_cols_mx"}
 
 MAX_MODULI = 15
 

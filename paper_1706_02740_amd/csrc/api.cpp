@@ -41,8 +41,8 @@ struct sft_plan_s {
     WorkspaceLayout wl;
     IoDesc ws_io;           // workspace slices (f and outputs unset)
     size_t footprint = 0;
-    size_t lds[SFT_KERNEL_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int blocks[SFT_KERNEL_COUNT] = {0, 0, 0, 0, 0, 0, 0};   // per transform; 0 = kernel not used
+    size_t lds[SFT_KERNEL_COUNT] = {};
+    int blocks[SFT_KERNEL_COUNT] = {};   // per transform; 0 = kernel not used
     bool split = false;     // short DFTs too large for one workgroup's LDS
     int device = 0;
     hipStream_t last_stream = nullptr;
@@ -129,9 +129,9 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     SigDesc& d = pl->hdesc;
     const size_t lds_cap = (size_t)lds_limit - 256;   // room for the kernels' static LDS
     const int path = p ? p->dft_path : 0;
-    if (path < 0 || path > 3) {
+    if (path < 0 || path > 4) {
         delete pl;
-        return fail(SFT_EINVAL, "dft_path must be 0, 1, 2 or 3");
+        return fail(SFT_EINVAL, "dft_path must be 0, 1, 2, 3 or 4");
     }
     const bool fits = dft_fits_one_workgroup(d) && dft_lds_bytes(d) <= lds_cap;
     const int mx = dft_mfma_variant(d);
@@ -144,7 +144,13 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         delete pl;
         return fail(SFT_EUNSUPPORTED, "the matrix-core short-DFT kernel does not cover this plan (use dft_path 0)");
     }
-    pl->split = path == 2 || (path == 0 && !fits && !mx_fits);
+    const bool cmx_fits = cols_mx_covers(d) && cols_mx_lds_bytes(d) <= lds_cap;
+    if (path == 4 && !cmx_fits) {
+        delete pl;
+        return fail(SFT_EUNSUPPORTED, "the matrix-core column kernel does not cover this plan (use dft_path 0 or 2)");
+    }
+    pl->split = path == 2 || path == 4 || (path == 0 && !fits && !mx_fits);
+    const bool cols_mx = pl->split && (path == 4 || (path == 0 && cmx_fits));
     pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
     d.vote_bitmap = identify_lds_bytes(d, true) <= lds_cap ? 1 : 0;
     // bit 32: the key vote; bit 33: phase identification (a batch takes each
@@ -167,13 +173,15 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         }
     } else {
         pl->lds[SFT_KERNEL_DFT_ROWS] = rows_lds_bytes(d);
-        pl->lds[SFT_KERNEL_DFT_COLS] = cols_lds_bytes(d);
+        if (cols_mx) pl->lds[SFT_KERNEL_DFT_COLS_MX] = cols_mx_lds_bytes(d);
+        else pl->lds[SFT_KERNEL_DFT_COLS] = cols_lds_bytes(d);
         // low 32 bits: the selection that reads E in every pass; above: the
         // one with the block's keys in LDS, 0 when they do not fit
         const size_t kbytes = select_lds_bytes(d, true);
         pl->lds[SFT_KERNEL_SELECT] = select_lds_bytes(d, false) | ((kbytes <= lds_cap ? kbytes : 0) << 32);
         pl->blocks[SFT_KERNEL_DFT_ROWS] = rows_blocks(d);
-        pl->blocks[SFT_KERNEL_DFT_COLS] = cols_blocks(d);
+        if (cols_mx) pl->blocks[SFT_KERNEL_DFT_COLS_MX] = cols_mx_blocks(d);
+        else pl->blocks[SFT_KERNEL_DFT_COLS] = cols_blocks(d);
         pl->blocks[SFT_KERNEL_SELECT] = select_blocks(d);
     }
     for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
@@ -243,10 +251,30 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
                     mxa[(((size_t)j * kMxSteps + st) * kMxTiles + m) * 64 + l] = v;
                 }
     }
+    // the split path's matrix-core columns: the same operands for up to
+    // kMxcSteps x kMxcTiles tiles (only when the plan uses that kernel)
+    const size_t n_mxc = pl->blocks[SFT_KERNEL_DFT_COLS_MX] ? (size_t)d.K * kMxcSteps * kMxcTiles * 64 : 0;
+    std::vector<float2> mxc(n_mxc, make_float2(0.f, 0.f));
+    for (int j = 0; j < d.K && n_mxc; ++j) {
+        const int pj = d.p[j], hj = (pj - 1) / 2;
+        for (int st = 0; st < kMxcSteps; ++st)
+            for (int m = 0; m < kMxcTiles; ++m)
+                for (int l = 0; l < 64; ++l) {
+                    const int n = 1 + 4 * st + l / 16, k = 16 * m + l % 16;
+                    float2 v = make_float2(0.f, 0.f);
+                    if (n <= hj && k == 0) {
+                        v = make_float2(1.f, 0.f);
+                    } else if (n <= hj && k <= hj) {
+                        const double ang = 2.0 * M_PI * (double)((n * k) % pj) / (double)pj;
+                        v = make_float2((float)cos(ang), (float)sin(ang));
+                    }
+                    mxc[(((size_t)j * kMxcSteps + st) * kMxcTiles + m) * 64 + l] = v;
+                }
+    }
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al((size_t)Qpad * 4);
-    const size_t b_trig = al(n_trig * 8), b_mxa = al(n_mxa * 8);
-    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa;
+    const size_t b_trig = al(n_trig * 8), b_mxa = al(n_mxa * 8), b_mxc = al(n_mxc * 8);
+    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa + b_mxc;
     hipError_t e = hipMalloc(&pl->tables, tbytes);
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(tables) failed"); }
     char* tb = static_cast<char*>(pl->tables);
@@ -256,6 +284,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     d.rate = reinterpret_cast<const float*>(tb + b_band + b_tws1 + b_twp);
     d.trig = reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate);
     d.mxa = reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate + b_trig);
+    d.mxc = n_mxc ? reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa) : nullptr;
     e = hipMemcpy(tb, band.data(), n_band * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band, tws1.data(), n_tws1 * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1, twp.data(), n_twp * 8, hipMemcpyHostToDevice);
@@ -264,6 +293,9 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate, trig.data(), n_trig * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate + b_trig, mxa.data(), n_mxa * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_mxc)
+        e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa, mxc.data(), n_mxc * 8,
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(tables)"); }
     e = hipMalloc(&pl->ddesc, sizeof(SigDesc));
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(descriptor) failed"); }
@@ -363,12 +395,12 @@ hipError_t launch_gather_l(const BatchArgs& a, int b, size_t taps, hipStream_t s
 hipError_t launch_merge_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_merge(a, b, st); }
 
 // Launch order of the pipeline and the launcher of each kernel id.
-const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER,    SFT_KERNEL_DFT_MX, SFT_KERNEL_DFT,
-                                      SFT_KERNEL_DFT_ROWS,  SFT_KERNEL_DFT_COLS, SFT_KERNEL_SELECT,
-                                      SFT_KERNEL_IDENTIFY,  SFT_KERNEL_MERGE};
+const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER,   SFT_KERNEL_DFT_MX,      SFT_KERNEL_DFT,
+                                      SFT_KERNEL_DFT_ROWS, SFT_KERNEL_DFT_COLS,    SFT_KERNEL_DFT_COLS_MX,
+                                      SFT_KERNEL_SELECT,   SFT_KERNEL_IDENTIFY,    SFT_KERNEL_MERGE};
 const char* kNames[SFT_KERNEL_COUNT] = {"launch(gather)",   "launch(dft)",      "launch(identify)",
                                         "launch(merge)",    "launch(dft_rows)", "launch(dft_cols)",
-                                        "launch(select)",   "launch(dft_mx)"};
+                                        "launch(select)",   "launch(dft_mx)",   "launch(dft_cols_mx)"};
 
 LaunchFn launcher(int k) {
     switch (k) {
@@ -379,6 +411,7 @@ LaunchFn launcher(int k) {
         case SFT_KERNEL_DFT_ROWS: return launch_dft_rows;
         case SFT_KERNEL_DFT_COLS: return launch_dft_cols;
         case SFT_KERNEL_DFT_MX: return launch_dft_mx;
+        case SFT_KERNEL_DFT_COLS_MX: return launch_dft_cols_mx;
         default: return launch_select;
     }
 }

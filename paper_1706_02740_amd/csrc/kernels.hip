@@ -995,10 +995,10 @@ __device__ __forceinline__ float lane_pair(float v) {
 // (at most NTW and MT).  bf: the block as floats.
 // At: the A operands in lane order ((st kMxTiles + m) 64 + lane, as the
 // plan's mxa table), in LDS.
-template <int MT, int NTW>
+template <int MT, int NTW, int ATILES = kMxTiles>
 __device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, int mt, int ntw, const float2* At,
                                          mf4 (&Cm)[NTW][MT], mf4 (&Dm)[NTW][MT]) {
-    static_assert(MT <= kMxTiles, "A operand tiles");
+    static_assert(MT <= ATILES, "A operand tiles");
     const int lane = (int)threadIdx.x & 63;
     const int wid = (int)threadIdx.x >> 6;
     const int li = lane & 15;
@@ -1017,7 +1017,7 @@ __device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, 
         const bool nin = n <= h;
         float2 av[MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) av[m] = At[(st * kMxTiles + m) * 64 + lane];
+        for (int m = 0; m < MT; ++m) av[m] = At[(st * ATILES + m) * 64 + lane];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             if (t >= ntw) break;
@@ -1352,6 +1352,95 @@ __global__ void __launch_bounds__(kThreads) k_dft_cols(BatchArgs a) {
     load_trig<kThreads>(trig, (p - 1) >> 1, glb(d->trig) + d->trig_off[j]);
     __syncthreads();
     dft_cols_lds<kThreads>(tile, C, C, p, trig, E + c0, s1, 1.0f / (float)P);
+}
+
+// Split path, step B on the matrix cores: block -> (modulus j, band b, 64
+// columns), 8 waves; in place on E.  The 64 columns of the tile are the
+// 128 real columns of pfa_mfma with one N-tile per wave (its s1 is the tile
+// width), the A operands come from the plan's larger table (h <= 47), and
+// the outputs are combined and stored exactly as in k_dft's matrix-core path,
+// so both give the same bins bit for bit.
+__global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
+    constexpr int NT = kDftThreads;
+    constexpr int C = 64;
+    static_assert(NT / 64 * 16 == 2 * C, "one N-tile per wave");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Where at = locate(a);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
+    const IoDesc io = io_of(a, at.sig);
+    const int tid = (int)threadIdx.x;
+    const int Q = d->Q;
+    const int s1 = d->s1;
+    const int lg = d->log2s1;
+    const int nc = s1 / C;
+    int blk = at.blk;
+    const bool shifted = blk >= d->K * Q * nc;   // phase identification: the shifted samples' bins
+    if (shifted) blk -= d->K * Q * nc;
+    const int j = blk / (Q * nc);
+    blk -= j * Q * nc;
+    const int b = blk / nc;
+    const int c0 = (blk - b * nc) * C;
+    const int p = d->p[j];
+    const int P = d->P[j];
+    const int h = (p - 1) >> 1;
+    int pmax = 0;
+    for (int jj = 0; jj < d->K; ++jj) pmax = max(pmax, d->p[jj]);
+    const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
+    float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]
+    float2* At = tile + (size_t)pmax * C;           // [kMxcSteps][kMxcTiles][64]
+    GLOBAL float2* __restrict__ E = glb(shifted ? io.E2 : io.E) + base;
+    const GLOBAL float2* __restrict__ A = glb(d->mxc) + (size_t)j * kMxcSteps * kMxcTiles * 64;
+    constexpr int U = 8;   // loads of a thread in flight before its LDS writes
+    for (int i0 = tid; i0 < p * C; i0 += U * NT) {
+        float2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * NT;
+            if (i < p * C) v[u] = ld2(E + ((size_t)(i / C) << lg) + c0 + (i % C));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * NT;
+            if (i < p * C) tile[i] = v[u];
+        }
+    }
+    for (int i = tid; i < kMxcSteps * kMxcTiles * 64; i += NT) At[i] = ld2(A + i);
+    __syncthreads();
+    constexpr int MT = kMxcTiles;
+    mf4 Cm[1][MT], Dm[1][MT];
+    const float* bf = reinterpret_cast<const float*>(tile);
+    const int mt = (h + 16) >> 4;
+    pfa_mfma<MT, 1, kMxcTiles>(bf, C, p, h, mt, 1, At, Cm, Dm);
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+    const int plane = li & 1;
+    const float sgn = plane ? -1.f : 1.f;
+    const float scale = 1.0f / (float)P;
+    const int N = 16 * wid + li;
+    const int c = c0 + (N >> 1);
+    const float x0v = bf[N];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m >= mt) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 16 * m + 4 * lk + r;
+            const float cv = Cm[0][m][r];
+            const float dp = lane_pair(Dm[0][m][r]);
+            const float xk = (x0v + cv + sgn * dp) * scale;
+            const float xm = (x0v + cv - sgn * dp) * scale;
+            const float xk2 = lane_pair(xk);
+            const float xm2 = lane_pair(xm);
+            const float re = plane ? xm2 : xk;
+            const float im = plane ? xm : xk2;
+            if (k <= h && (plane == 0 || k >= 1)) {
+                const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
+                st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));
+            }
+        }
+    }
 }
 
 // Split path, selection: one workgroup per (modulus j, band b), E in global
@@ -1945,6 +2034,17 @@ int rows_blocks(const SigDesc& d) {
     return n * (1 + d.phase);
 }
 int cols_blocks(const SigDesc& d) { return d.K * d.Q * (d.s1 / std::min(kColChunk, d.s1)) * (1 + d.phase); }
+int cols_mx_blocks(const SigDesc& d) { return d.K * d.Q * (d.s1 / 64) * (1 + d.phase); }
+bool cols_mx_covers(const SigDesc& d) {
+    int pmax = 0;
+    for (int j = 0; j < d.K; ++j) pmax = std::max(pmax, d.p[j]);
+    return d.s1 >= 64 && (pmax - 1) / 2 <= 4 * kMxcSteps && (pmax - 1) / 2 + 1 <= 16 * kMxcTiles;
+}
+size_t cols_mx_lds_bytes(const SigDesc& d) {
+    int pmax = 0;
+    for (int j = 0; j < d.K; ++j) pmax = std::max(pmax, d.p[j]);
+    return (size_t)pmax * 64 * 8 + (size_t)kMxcSteps * kMxcTiles * 64 * 8 + 64;
+}
 int select_blocks(const SigDesc& d) { return d.K * d.Q; }
 
 size_t rows_lds_bytes(const SigDesc& d) {
@@ -1972,7 +2072,7 @@ hipError_t configure_kernels(int max_lds) {
                          (const void*)k_identify<false, false>, (const void*)k_identify<true, false>,
                          (const void*)k_identify<false, true>, (const void*)k_identify<true, true>,
                          (const void*)k_merge, (const void*)k_dft_rows,
-                         (const void*)k_dft_cols, (const void*)k_select<kThreads, false>,
+                         (const void*)k_dft_cols, (const void*)k_dft_cols_mx, (const void*)k_select<kThreads, false>,
                          (const void*)k_select<kSelLdsThreads, true>};
     for (const void* k : ks) {
         hipFuncAttributes fa;
@@ -2010,6 +2110,11 @@ hipError_t launch_dft_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t
 
 hipError_t launch_dft_rows(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(k_dft_rows, dim3(blocks), dim3(kThreads), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_cols_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(k_dft_cols_mx, dim3(blocks), dim3(kDftThreads), lds, st, a);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ constexpr int kMaxDepth = 8;           // class-list length bound (depth^G <= 64
 constexpr int kSelBins = 1024;         // buckets of one radix-select pass (10-bit digits)
 constexpr int kMxSteps = 8;            // K-steps (4 values of n each) of the matrix-core p-point step: h <= 32
 constexpr int kMxTiles = 2;            // M-tiles (16 values of k each): h + 1 <= 32
+constexpr int kMxcSteps = 12;          // the split path's matrix-core columns: h <= 48
+constexpr int kMxcTiles = 3;           // h + 1 <= 48
 constexpr int kDftKBMax = 16;          // p-point output pairs per thread in the in-LDS short-DFT kernel
 constexpr int kSelLdsThreads = 1024;   // workgroup size of the split path's selection with its keys in LDS
 constexpr int kSelLdsMaxBlocks = 256;  // launches up to this many selection blocks (one per CU) take it
@@ -71,6 +73,9 @@ struct SigDesc {
     // lane l of step st, tile m: n = 1 + 4 st + l / 16, k = 16 m + l % 16 ->
     // (cos, sin)(2 pi (n k mod p) / p) for n, k in [1, h]; (1, 0) for k = 0 < n <= h; else 0
     const float2* mxa;
+    // [K][kMxcSteps][kMxcTiles][64]: the same operands for the split path's
+    // matrix-core column kernel (null when the plan does not use it)
+    const float2* mxc;
 };
 
 // Per-transform pointers: input, outputs and workspace slices.
@@ -140,6 +145,11 @@ size_t select_lds_bytes(const SigDesc& d, bool lds_keys);   // with the block's 
 hipError_t launch_dft_rows(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_dft_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_dft_cols(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+// the split path with its p-point step on the matrix cores (s1 >= 64, every h <= 47)
+int cols_mx_blocks(const SigDesc& d);
+bool cols_mx_covers(const SigDesc& d);
+size_t cols_mx_lds_bytes(const SigDesc& d);
+hipError_t launch_dft_cols_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_merge(const BatchArgs& a, int blocks, hipStream_t st);
 hipError_t configure_kernels(int max_lds);

@@ -1,11 +1,11 @@
 """Autotuning of the short-DFT path per plan shape, with an on-disk cache.
 
 For a plan shape (N, s, parameters) and a batch size, every short-DFT path
-the library accepts for it (1: VALU in LDS, 2: split, 3: matrix cores in LDS;
-see sft_params.dft_path) is timed on a synthetic input with HIP events on the
+the library accepts for it (1: VALU in LDS, 2: split, 3: matrix cores in LDS,
+4: split with matrix-core columns; see sft_params.dft_path) is timed on a synthetic input with HIP events on the
 launch stream, and the fastest is kept.  All paths compute the same
-transform; paths 1 and 2 give bitwise equal results, path 3 sums the p-point
-step in another order.  Results are cached per device architecture, plan
+transform; paths 1 and 2 give bitwise equal results, as do paths 3 and 4,
+which sum the p-point step in another order.  Results are cached per device architecture, plan
 shape and batch-size class in a JSON file (``$SFT_TUNE_CACHE``, default
 ``~/.cache/paper_1706_02740_amd/tune.json``), so a shape is measured once.
 """
@@ -15,7 +15,7 @@ import json
 import os
 from typing import Callable, Dict, Optional
 
-PATHS = (3, 1, 2)   # tried in this order; ties keep the earlier one
+PATHS = (3, 1, 4, 2)   # tried in this order; ties keep the earlier one
 
 
 def cache_path() -> str:

@@ -72,6 +72,8 @@ INTERMEDIATE_CASES = [
     ("valu_n2e16_s40_10db", 2 ** 16, 40, 10.0, {"dft_path": 1}, 6),
     ("split_prime_n100003_s20_30db", 100_003, 20, 30.0, {"dft_path": 2}, 1),
     ("split_n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2, "dft_path": 2}, 3),
+    ("splitmx_prime_n100003_s20_30db", 100_003, 20, 30.0, {"dft_path": 4}, 1),
+    ("auto_splitmx_n2e20_s100_30db", 2 ** 20, 100, 30.0, {}, 7),   # three row tiles (h = 41)
 ]
 
 
@@ -297,6 +299,25 @@ def test_split_dft_path_equals_in_lds_path(gpu, N, s, snr, kw):
     f = dev(sg.f32)
     res = []
     for path in (1, 2):
+        plan = gpu.Plan(N, s, dft_path=path, **kw)
+        w, c, n = plan.execute(f)
+        torch.cuda.synchronize()
+        res.append((w.cpu().numpy(), c.cpu().numpy(), plan.fetch(gpu.FETCH_BINS), plan.fetch(gpu.FETCH_HEAVY)))
+    for x, y in zip(res[0], res[1]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("N,s,snr,kw", [(2 ** 16, 40, 10.0, {}), (100_003, 20, 20.0, {}),
+                                        (2 ** 14, 32, None, {"ident": "phase"})])
+def test_split_matrix_core_path_equals_in_lds_matrix_core_path(gpu, N, s, snr, kw):
+    """The split path with matrix-core columns performs the p-point step with
+    the same operands in the same order as the in-LDS matrix-core kernel:
+    bins, heavy sets and outputs are bitwise equal."""
+    say("split mx vs lds mx", N, s, kw)
+    sg = siggen.sparse_signal(N, s, seed=21, snr_db=snr)
+    f = dev(sg.f32)
+    res = []
+    for path in (3, 4):
         plan = gpu.Plan(N, s, dft_path=path, **kw)
         w, c, n = plan.execute(f)
         torch.cuda.synchronize()

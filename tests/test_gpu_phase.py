@@ -24,6 +24,7 @@ CASES = [
     ("mx_n2e16_s40_10db", 2 ** 16, 40, 10.0, {"dft_path": 3}, 6),
     ("valu_n2e16_s40_10db", 2 ** 16, 40, 10.0, {"dft_path": 1}, 6),
     ("split_prime_n100003_s20_30db", 100_003, 20, 30.0, {"dft_path": 2}, 1),
+    ("splitmx_n2e16_s40_10db", 2 ** 16, 40, 10.0, {"dft_path": 4}, 6),
     ("kappa12_n3001_s5_40db", 3001, 5, 40.0, {"kappa": 12}, 2),
     ("n31_s1", 31, 1, None, {}, 4),
 ]

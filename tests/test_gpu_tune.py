@@ -18,9 +18,9 @@ def test_tuned_plan_and_cache(gpu, tmp_path):
     N, s = 2 ** 16, 40
     say("tune", N, s)
     path = tune.best_dft_path(N, s, batch=8, cache=cache)
-    assert path in (1, 2, 3)
+    assert path in (1, 2, 3, 4)
     entry = next(iter(cache.data.values()))
-    assert set(entry["ms_per_transform"]) == {"1", "2", "3"}   # every path fits this shape
+    assert set(entry["ms_per_transform"]) == {"1", "2", "3", "4"}   # every path fits this shape
     tuned = tune.tuned_plan(N, s, batch=8, cache=cache)
     explicit = gpu.Plan(N, s, dft_path=path)
     f = dev(siggen.sparse_signal(N, s, seed=4, snr_db=20.0).f32)

@@ -9,7 +9,7 @@ from paper_1706_02740_amd import tune
 
 def test_choose_takes_the_fastest_and_skips_refused_paths(tmp_path):
     cache = tune.Cache(str(tmp_path / "t.json"))
-    times = {1: 2.0, 2: 1.5, 3: None}
+    times = {1: 2.0, 2: 1.5, 3: None, 4: None}
     entry = tune.choose("k", lambda p: times[p], cache)
     assert entry["dft_path"] == 2
     assert entry["ms_per_transform"] == {"1": 2.0, "2": 1.5}
@@ -26,7 +26,7 @@ def test_cache_is_reused_and_persisted(tmp_path):
 
     def measure(p):
         calls.append(p)
-        return {1: 3.0, 2: 4.0, 3: 2.5}[p]
+        return {1: 3.0, 2: 4.0, 3: 2.5, 4: 3.5}[p]
 
     assert tune.choose("k", measure, tune.Cache(path))["dft_path"] == 3
     n = len(calls)
