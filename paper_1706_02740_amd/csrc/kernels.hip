@@ -796,15 +796,17 @@ __device__ int block_exclusive_sum(int v, int32_t* part) {
     return base + x - v;
 }
 
-// Heavy bins of one block (keys >= thr, at most T of them).  Writes the
-// threshold, the heavy bins in ascending Good-Thomas position (H), and for
-// every residue class c mod s1 (column c of the [p][s1] layout) the `depth`
-// heaviest heavy bins of the class in descending key order (CL[c * depth + e],
-// -1 where fewer).  Wave w walks the contiguous positions [w seg, (w + 1) seg)
-// 64 at a time; a ballot per step gives each heavy bin its rank within the
-// wave, a scan of the per-wave counts its rank in the block, so H comes out in
-// position order without sorting.  Class ranks come from pairwise key
-// comparisons of the heavy (key, position) pairs (hk), split over all threads.
+// Heavy bins among the keys key(0..P-1) of one block (keys >= thr, at most T
+// of them; the keys are those of every bin, or a candidate list that holds
+// the heavy ones).  Writes the threshold, the heavy bins in the order of the
+// index i (H), and for every residue class c mod s1 (the bin mod s1, column c
+// of the [p][s1] layout) the `depth` heaviest heavy bins of the class in
+// descending key order (CL[c * depth + e], -1 where fewer).  Wave w walks the
+// contiguous indices [w seg, (w + 1) seg) 64 at a time; a ballot per step
+// gives each heavy bin its rank within the wave, a scan of the per-wave
+// counts its rank in the block, so H comes out in index order without
+// sorting.  Class ranks come from pairwise key comparisons of the heavy
+// (key, index) pairs (hk), split over all threads.
 // scr: LDS int32[kSelBins]; part: LDS int32[NT / 64]; hk: LDS uint64[2 T];
 // cl: LDS int32[s1 * depth].
 template <int NT, class KeyF>
@@ -817,6 +819,8 @@ __device__ void emit_heavy(KeyF key, int P, int T, int s1, int depth, uint64_t t
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const uint64_t lt = ((uint64_t)1 << lane) - 1;
+    // residue class of a key: its bin mod s1 (the Good-Thomas column)
+    auto class_of = [s1](uint64_t k) { return (int)((0xffffffffu - (uint32_t)(k & 0xffffffffu)) & (uint32_t)(s1 - 1)); };
     const int seg = ((P + NT - 1) / NT) * 64;   // positions per wave, a multiple of 64
     const int p0 = wid * seg;
     const int p1 = min(P, p0 + seg);
@@ -862,10 +866,10 @@ __device__ void emit_heavy(KeyF key, int P, int T, int s1, int depth, uint64_t t
             const int q = it / n;          // lanes of a wave share q: the hk reads are broadcasts
             const int e = it - q * n;
             const uint64_t k = hk[2 * e];
-            const int cls = (int)hk[2 * e + 1] & (s1 - 1);
+            const int cls = class_of(k);
             const int f1 = min(n, (q + 1) * span);
             int c = 0;
-            for (int f = q * span; f < f1; ++f) c += (((int)hk[2 * f + 1] & (s1 - 1)) == cls && hk[2 * f] > k) ? 1 : 0;
+            for (int f = q * span; f < f1; ++f) c += (class_of(hk[2 * f]) == cls && hk[2 * f] > k) ? 1 : 0;
             if (c) atomicAdd(&heavier[e], c);
         }
         __syncthreads();
@@ -873,15 +877,15 @@ __device__ void emit_heavy(KeyF key, int P, int T, int s1, int depth, uint64_t t
             const int r = heavier[e];
             if (r < depth) {
                 const uint64_t k = hk[2 * e];
-                cl[((int)hk[2 * e + 1] & (s1 - 1)) * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+                cl[class_of(k) * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
             }
         }
     } else {
         for (int e = tid; e < n; e += NT) {
             const uint64_t k = hk[2 * e];
-            const int cls = (int)hk[2 * e + 1] & (s1 - 1);
+            const int cls = class_of(k);
             int r = 0;
-            for (int f = 0; f < n; ++f) r += (((int)hk[2 * f + 1] & (s1 - 1)) == cls && hk[2 * f] > k) ? 1 : 0;
+            for (int f = 0; f < n; ++f) r += (class_of(hk[2 * f]) == cls && hk[2 * f] > k) ? 1 : 0;
             if (r < depth) cl[cls * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
         }
     }
@@ -1485,6 +1489,116 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
         }
         __syncthreads();
     }
+    const size_t blk = (size_t)(j * Q + b);
+    GLOBAL int32_t* __restrict__ Hout = glb(io.H) + blk * d->T;
+    GLOBAL uint64_t* __restrict__ thr_out = glb(io.thr) + blk;
+    GLOBAL int32_t* __restrict__ CLout = glb(io.CL) + blk * (size_t)s1 * d->depth;
+    if constexpr (!LDSKEYS) {
+        // Two reads of E instead of one per radix pass and two more for the
+        // emission: the first pass finds the bucket (key bits 62..53) of the
+        // T-th largest key; every key in it or above goes to a candidate list
+        // in LDS (keys[] as uint64), which holds the T largest; selection and
+        // emission run on the list.  A list longer than its capacity leaves
+        // the block to the passes over E below.
+        uint64_t* cand = reinterpret_cast<uint64_t*>(keys);
+        const int cap = d->sel_cap;
+        const int tid = (int)threadIdx.x;
+        const int lane = tid & 63;
+        const int wid = tid >> 6;
+        __shared__ int32_t sh_nc, sh_dig;
+        __shared__ unsigned long long sh_min;
+        constexpr int U = 4;   // loads of a thread in flight at once
+        auto hi_of = [](float2 e) { return __float_as_uint(fmaf(e.x, e.x, e.y * e.y)); };
+        if (tid == 0) {
+            sh_nc = 0;
+            sh_dig = 0;
+            sh_min = ~0ull;
+        }
+        const bool all = d->T >= P;
+        if (!all) {
+            for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
+            __syncthreads();
+            for (int base = 0; base < P; base += U * NT) {
+                float2 ev[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = base + u * NT + tid;
+                    ev[u] = i < P ? ld2(E + i) : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (base + u * NT + tid < P) atomicAdd(&hist[hi_of(ev[u]) >> 21], 1);
+            }
+            __syncthreads();
+            // the bucket holding rank T, scanning the buckets in descending order
+            constexpr int BPT = kSelBins / NT;
+            int cnt[BPT];
+            int loc = 0;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                cnt[q] = hist[kSelBins - 1 - (tid * BPT + q)];
+                loc += cnt[q];
+            }
+            const int x = wave_inclusive_sum(loc);
+            if (lane == 63) part[wid] = x;
+            __syncthreads();
+            int run = waves_before<NT>(part, wid) + x - loc;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                if (run < d->T && run + cnt[q] >= d->T) sh_dig = kSelBins - 1 - (tid * BPT + q);
+                run += cnt[q];
+            }
+        }
+        __syncthreads();
+        const uint32_t dig = (uint32_t)sh_dig;
+        const uint64_t ltm = ((uint64_t)1 << lane) - 1;
+        for (int base = 0; base < P; base += U * NT) {   // wave-uniform trip count
+            float2 ev[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = base + u * NT + tid;
+                ev[u] = i < P ? ld2(E + i) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = base + u * NT + tid;
+                const uint32_t h = hi_of(ev[u]);
+                const bool take = i < P && (h >> 21) >= dig;
+                const uint64_t m = __ballot(take);
+                int wb = 0;
+                if (lane == 0 && m) wb = atomicAdd(&sh_nc, __popcll(m));
+                wb = __shfl(wb, 0);
+                if (take) {
+                    const int pos = wb + __popcll(m & ltm);
+                    if (pos < cap)
+                        cand[pos] = ((uint64_t)h << 32) | (uint64_t)(0xffffffffu - pfa_bin(i, lg, s1, (uint32_t)P, cA, cB));
+                }
+            }
+        }
+        __syncthreads();
+        const int nc = sh_nc;
+        if (nc <= cap) {   // uniform over the block
+            uint64_t thr = 0;
+            if (!all) {
+                if (nc > d->T) {
+                    auto each_c = [&](auto f) {
+                        for (int i = tid; i < nc; i += NT) {
+                            const uint64_t k = cand[i];
+                            f((uint32_t)(k >> 32), [k] { return k; });
+                        }
+                    };
+                    thr = kth_largest<NT>(each_c, nc, d->T, hist, part);
+                } else {   // exactly the T largest: the threshold is the least of them
+                    for (int i = tid; i < nc; i += NT) atomicMin(&sh_min, (unsigned long long)cand[i]);
+                    __syncthreads();
+                    thr = sh_min;
+                }
+            }
+            emit_heavy<NT>([&](int i) { return cand[i]; }, nc, d->T, s1, d->depth, thr, hk, hist, part, cl, Hout,
+                           thr_out, CLout);
+            return;
+        }
+    }
     auto kf = [&](int i) {
         const uint32_t bin = pfa_bin(i, lg, s1, (uint32_t)P, cA, cB);
         if constexpr (LDSKEYS) return ((uint64_t)keys[i] << 32) | (uint64_t)(0xffffffffu - bin);
@@ -1502,9 +1616,7 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
         }
     };
     const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
-    const size_t blk = (size_t)(j * Q + b);
-    emit_heavy<NT>(kf, P, d->T, s1, d->depth, thr, hk, hist, part, cl, glb(io.H) + blk * d->T,
-                   glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
+    emit_heavy<NT>(kf, P, d->T, s1, d->depth, thr, hk, hist, part, cl, Hout, thr_out, CLout);
 }
 
 // ---------------------------------------------------------- k_identify ----
@@ -2061,7 +2173,7 @@ size_t select_lds_bytes(const SigDesc& d, bool lds_keys) {
     int32_t Pmax = 0;
     for (int j = 0; j < d.K; ++j) Pmax = d.P[j] > Pmax ? d.P[j] : Pmax;
     return kSelBins * 4 + 64 + (size_t)d.T * 16 + (((size_t)d.s1 * d.depth + 3) & ~(size_t)3) * 4 +
-           (lds_keys ? (size_t)Pmax * 4 : 0) + 64;
+           (lds_keys ? (size_t)Pmax * 4 : (size_t)d.sel_cap * 8) + 64;
 }
 
 // Dynamic LDS above 64 KiB: raise each kernel's limit where the runtime asks

@@ -164,6 +164,9 @@ void fill_desc(const sft_plan_info& in, SigDesc* d) {
     d->Tpow2 = tp;
     d->depth = in.depth;
     d->phase = in.ident == SFT_IDENT_PHASE ? 1 : 0;
+    int sc = 1024;
+    while (sc < 4 * in.T && sc < 4096) sc *= 2;
+    d->sel_cap = sc;
     d->M = (int32_t)in.M;
     int ac = 256;
     while (ac < 8 * in.s && ac < kAcceptCap) ac *= 2;

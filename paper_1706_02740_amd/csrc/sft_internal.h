@@ -43,6 +43,7 @@ struct SigDesc {
     int32_t accept_cap;     // accepted candidates one band may hold: min(4096, pow2 >= 8 s)
     int32_t vote_bitmap;    // 1: the heavy-bin bitmaps of identify fit the LDS; 0: identify must vote from bin keys
     int32_t phase;          // 1: phase identification (samples and bins also at the nodes moved one grid step)
+    int32_t sel_cap;        // candidate keys the split path's selection keeps in LDS: pow2 >= 4 T in [1024, 4096]
     float   inv2sig2;       // 1 / (2 sigma_t^2)
     float   wnorm;          // 1 / (2 pi sigma_t): W(v) = wnorm exp(-v^2 inv2sig2)
     float   gtap[kFastTaps];  // exp(-(i - kappa)^2 inv2sig2), i < taps (taps <= kFastTaps)

@@ -326,6 +326,36 @@ def test_split_matrix_core_path_equals_in_lds_matrix_core_path(gpu, N, s, snr, k
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("kind", ["noise", "impulse"])
+def test_split_selection_variants_agree(gpu, kind):
+    """The split path's selection has three forms: keys read once into LDS
+    (a launch of at most one block per CU: a single transform), a candidate
+    list of the keys at or above the T-th largest key's bucket (larger
+    launches), and passes over E (when the list overflows, as for an impulse,
+    whose bins all have one magnitude).  A batch of four and the single
+    calls give the same outputs bit for bit."""
+    N, s = 2 ** 18, 64
+    plan = gpu.Plan(N, s, dft_path=2)
+    if kind == "noise":
+        fs = [dev(siggen.sparse_signal(N, s, seed=40 + i, snr_db=10.0).f32) for i in range(4)]
+    else:
+        imp = np.zeros(N, np.complex64)
+        fs = []
+        for i in range(4):
+            imp[:] = 0
+            imp[1000 * i] = 1.0
+            fs.append(dev(imp))
+    say("split selection variants", kind)
+    outs, counts = gpu.execute_many([plan] * 4, fs)
+    torch.cuda.synchronize()
+    for i, f in enumerate(fs):
+        w, c, n = plan.execute(f)
+        torch.cuda.synchronize()
+        assert int(counts[i].item()) == int(n.item()), i
+        assert np.array_equal(outs[i][0].cpu().numpy(), w.cpu().numpy()), i
+        assert np.array_equal(outs[i][1].cpu().numpy(), c.cpu().numpy()), i
+
+
 def test_repeat_runs_are_bitwise_identical(gpu):
     sg = siggen.sparse_signal(2 ** 16, 30, seed=77, snr_db=10.0)
     plan = gpu.Plan(sg.N, sg.s)
