@@ -75,13 +75,14 @@ extern "C" {
  * (default 1: s1 = least power of two >= 2 s); group is G, the number of
  * primes per CRT tuple (default max(2, ceil(log2(N/s1)/6))); heavy_T is the
  * number of heavy bins kept per short DFT (default 2 s).  dft_path chooses the
- * short-DFT kernels: 0 = automatic (a whole block in LDS with the p-point
- * step on the matrix cores when s1 is 64 or 128 and every (p_j - 1)/2 < 32,
- * else in LDS on the vector ALUs when it fits, else the split path),
- * 1 = in LDS on the vector ALUs, 2 = split, 3 = in LDS on the matrix cores,
- * 4 = split with the p-point step on the matrix cores (s1 >= 64, every
- * (p_j - 1)/2 <= 47); automatic takes 4 for plans it would split when it
- * covers them.  Paths 1 and 2 give bitwise equal results, and so do paths 3
+ * short-DFT kernels: 1 = a whole block in LDS, p-point step on the vector
+ * ALUs; 2 = split (row FFTs, p-point columns and selection as separate
+ * kernels over HBM); 3 = a whole block in LDS, p-point step on the matrix
+ * cores (s1 = 64 or 128, every (p_j - 1)/2 < 32); 4 = split with the p-point
+ * step on the matrix cores (s1 >= 64, every (p_j - 1)/2 <= 47); 0 = automatic:
+ * 3 when it covers the plan, else 1 when two of its workgroups fit a CU's
+ * LDS, else 4 when it covers the plan, else 2 (sft_plan_info.dft_path reports
+ * the choice).  Paths 1 and 2 give bitwise equal results, and so do paths 3
  * and 4; the matrix-core paths sum the p-point step in another order.
  * ident chooses the identification (SFT_IDENT_*).  SFT_IDENT_PHASE is the
  * phase-shift family that Section 5 pairs with CLW-DSFT (whose inner algorithm
@@ -135,7 +136,7 @@ typedef struct sft_plan_info {
     double  c2;
     double  r;
     int32_t primes[SFT_MAX_MODULI];
-    int32_t reserved2;
+    int32_t dft_path;   /* short-DFT path the plan runs (1-4; 0 from sft_plan_describe) */
     int64_t P[SFT_MAX_MODULI];
     int64_t M;          /* sum of P[j]: nodes per band */
 } sft_plan_info;

@@ -90,7 +90,7 @@ class PlanInfo(ctypes.Structure):
                 ("ident", ctypes.c_int32), ("sigma_t", ctypes.c_double), ("beta", ctypes.c_double),
                 ("c1", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("c2", ctypes.c_double), ("r", ctypes.c_double),
-                ("primes", ctypes.c_int32 * MAX_MODULI), ("reserved2", ctypes.c_int32),
+                ("primes", ctypes.c_int32 * MAX_MODULI), ("dft_path", ctypes.c_int32),
                 ("P", ctypes.c_int64 * MAX_MODULI), ("M", ctypes.c_int64)]
 
 
@@ -167,7 +167,7 @@ def make_params(preset=PRESET_DMSFT6, kappa=0, sigma_t=0.0, tau=0.0, r=0.0, s1_m
 def _info_dict(info: PlanInfo) -> dict:
     K = info.K
     d = {name: getattr(info, name) for name, _ in PlanInfo._fields_
-         if name not in ("primes", "P", "reserved2")}
+         if name not in ("primes", "P")}
     d["primes"] = tuple(int(info.primes[j]) for j in range(K))
     d["P"] = tuple(int(info.P[j]) for j in range(K))
     d["q"] = tuple(info.q_first + 2 * b * info.L for b in range(info.Q))

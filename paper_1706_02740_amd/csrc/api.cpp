@@ -149,7 +149,10 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         delete pl;
         return fail(SFT_EUNSUPPORTED, "the matrix-core column kernel does not cover this plan (use dft_path 0 or 2)");
     }
-    pl->split = path == 2 || path == 4 || (path == 0 && !fits && !mx_fits);
+    // automatic: the in-LDS VALU kernel only while two of its workgroups fit
+    // a CU (with one, the split kernels are faster: measured by the tuner)
+    const bool valu_auto = fits && dft_lds_bytes(d) <= (size_t)lds_limit / 2;
+    pl->split = path == 2 || path == 4 || (path == 0 && !mx_fits && !valu_auto);
     const bool cols_mx = pl->split && (path == 4 || (path == 0 && cmx_fits));
     pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
     d.vote_bitmap = identify_lds_bytes(d, true) <= lds_cap ? 1 : 0;
@@ -161,6 +164,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     pl->blocks[SFT_KERNEL_GATHER] = gather_blocks(d);
     pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);
     pl->blocks[SFT_KERNEL_MERGE] = merge_blocks(d);
+    pl->info.dft_path = pl->split ? (cols_mx ? 4 : 2) : (path == 3 || (path == 0 && mx_fits)) ? 3 : 1;
     if (!pl->split) {
         const bool use_mx = path == 3 || (path == 0 && mx_fits);
         if (use_mx) {
