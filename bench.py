@@ -363,8 +363,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the transform would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path, so --gpus must be 1 "
+              "(independent transforms would be spread over GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch

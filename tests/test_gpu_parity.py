@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded complex64 inputs.
 
-Tolerances (derived in the design doc from the FP32 arithmetic of each step).
+Tolerances (derived from the FP32 arithmetic of each step).
 FP32 rounding errors scale with the magnitudes summed, not with a result that
 cancels, so each block's scale is  A = max(max|S_oracle|, max|f| * sum_i W_i)
 (sum_i W_i ~ 1/sqrt(2 pi) is the window's total weight):
