@@ -52,6 +52,14 @@ __device__ __forceinline__ void st2(GLOBAL float2* p, float2 v) {
     w.y = v.y;
     *(GLOBAL pod_f2*)p = w;
 }
+// Streaming store: data written once and read once later by another kernel
+// (samples, bins), kept from displacing reusable lines in the caches.
+__device__ __forceinline__ void st2s(GLOBAL float2* p, float2 v) {
+    pod_f2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (GLOBAL pod_f2*)p);
+}
 // a * b with both multiply-adds spelled out: every kernel that inlines it
 // rounds the same way (no contraction left to the compiler's choice), which
 // keeps the kernels that must agree bit for bit in agreement.
@@ -74,7 +82,7 @@ __device__ __forceinline__ void copy_to_lds(float2* dst, const GLOBAL float2* sr
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u * NT;
-            if (i < n4) v[u] = s4[i];
+            if (i < n4) v[u] = __builtin_nontemporal_load(s4 + i);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -233,7 +241,7 @@ __device__ __forceinline__ void store_bands(GLOBAL float2* __restrict__ S, int P
             } else {
                 ph = cmul(ph, step);
             }
-            st2(S + (size_t)(b0 + bb) * P, cmul(acc[bb], ph));
+            st2s(S + (size_t)(b0 + bb) * P, cmul(acc[bb], ph));
         }
     }
 }
@@ -307,7 +315,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             const GLOBAL f4u* w4 = (const GLOBAL f4u*)(f + (jc - kappa));
 #pragma unroll
             for (int i = 0; i + 1 < TAPS; i += 2) {
-                const f4u v = w4[i >> 1];
+                const f4u v = w4[i >> 1];   // plain loads: a thread's next load reads the same line
                 x[i] = make_float2(v.x, v.y);
                 x[i + 1] = make_float2(v.z, v.w);
             }
@@ -353,7 +361,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                     } else {
                         ph = cmul(ph, step);
                     }
-                    st2(S + (size_t)b * P, cmul(acc[bb], ph));
+                    st2s(S + (size_t)b * P, cmul(acc[bb], ph));
                 }
             }
         }
@@ -675,13 +683,13 @@ __device__ void dft_cols_lds(const float2* blk, int stride, int ncols, int p, co
         for (int kk = 0; kk < kDftKB; ++kk) {
             const int k = k0 + kk;
             if (k <= h) {
-                st2(out + (size_t)k * out_stride + c,
+                st2s(out + (size_t)k * out_stride + c,
                     make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale));
-                st2(out + (size_t)(p - k) * out_stride + c,
+                st2s(out + (size_t)(p - k) * out_stride + c,
                     make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale));
             }
         }
-        if (g == 0) st2(out + c, make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale));
+        if (g == 0) st2s(out + c, make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale));
     }
 }
 
@@ -1177,7 +1185,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
                     // even lanes store X_k, odd lanes X_{p-k} (X_0 once, by the even lane)
                     if (k <= h && (plane == 0 || k >= 1)) {
                         const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
-                        st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));
+                        st2s(E + (row << lg) + (uint32_t)c, make_float2(re, im));
                         valid |= (uint64_t)1 << q;
                     }
                 }
@@ -1199,8 +1207,8 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         if (kk < KB && k <= h) {
             const float2 xk = make_float2((x0.x + C[kk].x + D[kk].y) * scale, (x0.y + C[kk].y - D[kk].x) * scale);
             const float2 xm = make_float2((x0.x + C[kk].x - D[kk].y) * scale, (x0.y + C[kk].y + D[kk].x) * scale);
-            st2(E + (k << lg) + c, xk);
-            st2(E + ((p - k) << lg) + c, xm);
+            st2s(E + (k << lg) + c, xk);
+            st2s(E + ((p - k) << lg) + c, xm);
             hi[2 * kk] = __float_as_uint(fmaf(xk.x, xk.x, xk.y * xk.y));
             hi[2 * kk + 1] = __float_as_uint(fmaf(xm.x, xm.x, xm.y * xm.y));
             valid |= (uint64_t)3 << (2 * kk);
@@ -1209,7 +1217,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     hi[NK - 1] = 0;
     if (g == 0) {
         const float2 xz = make_float2((x0.x + sa.x) * scale, (x0.y + sa.y) * scale);
-        st2(E + c, xz);
+        st2s(E + c, xz);
         hi[NK - 1] = __float_as_uint(fmaf(xz.x, xz.x, xz.y * xz.y));
         valid |= (uint64_t)1 << (NK - 1);
     }
@@ -1306,7 +1314,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     else
         fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
     GLOBAL float2* __restrict__ X = glb(shifted ? io.E2 : io.E) + base;   // the bins' buffer holds the step-A result
-    for (int i = tid; i < n; i += kThreads) st2(X + i, buf[i]);
+    for (int i = tid; i < n; i += kThreads) st2s(X + i, buf[i]);
 }
 
 // Split path, step B: block -> (modulus j, band b, 64 columns); in place on E.
@@ -1441,7 +1449,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
             const float im = plane ? xm : xk2;
             if (k <= h && (plane == 0 || k >= 1)) {
                 const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
-                st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));
+                st2s(E + (row << lg) + (uint32_t)c, make_float2(re, im));
             }
         }
     }
