@@ -1185,7 +1185,9 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
                     // even lanes store X_k, odd lanes X_{p-k} (X_0 once, by the even lane)
                     if (k <= h && (plane == 0 || k >= 1)) {
                         const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
-                        st2s(E + (row << lg) + (uint32_t)c, make_float2(re, im));
+                        // plain store: two waves fill each 128-byte line of E here, which
+                        // the L2 combines (a streaming store writes the halves separately)
+                        st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));
                         valid |= (uint64_t)1 << q;
                     }
                 }
@@ -1449,7 +1451,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
             const float im = plane ? xm : xk2;
             if (k <= h && (plane == 0 || k >= 1)) {
                 const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
-                st2s(E + (row << lg) + (uint32_t)c, make_float2(re, im));
+                st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));   // two waves per line: plain
             }
         }
     }
