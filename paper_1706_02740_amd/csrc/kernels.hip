@@ -2071,18 +2071,19 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
     const int total = block_exclusive_scan(off, Q, scratch);
     const int n = min(total, kMergeCap);
     if (tid == 0 && total > kMergeCap) atomicOr(io.status, kStatusMergeOverflow);
-    for (int bb = 0; bb < Q; ++bb) {
-        const int cnt = glb(io.Rn)[bb];
-        const int o = off[bb];
-        for (int k = tid; k < cnt; k += kThreads) {
-            const int dst = o + k;
-            if (dst < n) {
-                const double2 v = ldd2(glb(io.Rv) + (size_t)bb * s + k);
-                mm[dst] = v.x * v.x + v.y * v.y;
-                ww[dst] = glb(io.Rw)[(size_t)bb * s + k];
-                src[dst] = bb * s + k;
-            }
+    // entry e of the concatenation belongs to the last band bb with off[bb] <= e
+    // (a band with off[bb] <= e < off[bb + 1] is not empty); all loads at once
+    for (int e = tid; e < n; e += kThreads) {
+        int lo = 0, hi = Q - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= e) lo = mid; else hi = mid - 1;
         }
+        const int k = e - off[lo];
+        const double2 v = ldd2(glb(io.Rv) + (size_t)lo * s + k);
+        mm[e] = v.x * v.x + v.y * v.y;
+        ww[e] = glb(io.Rw)[(size_t)lo * s + k];
+        src[e] = lo * s + k;
     }
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
