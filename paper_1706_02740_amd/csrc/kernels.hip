@@ -1806,17 +1806,14 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
 
     // 2. candidates -> vote -> median
     const bool small_n = d->N <= ((int64_t)1 << 31);   // then B lies in the int32 range
-    for (int c = tid; c < total; c += kThreads) {
-        int64_t w;
-        int t = 0, jp = 0;   // CRT tuple (residue identification); producing modulus (phase)
-        if (PHASE && phase) {
-            jp = c / T;
-            const int e = c - jp * T;
-            const int h0 = Hall[(size_t)(jp * Q + b) * T + e];
-            const size_t at0 = (size_t)Q * d->Moff[jp] + (size_t)b * d->P[jp] +
-                               ((size_t)(h0 % d->p[jp]) << lg) + (size_t)(h0 & (s1 - 1));
-            if (!phase_frequency(ld2(Eall + at0), ld2(glb(io.E2) + at0), h0, d->P[jp], d->N, lo, hi, w)) continue;
-        } else {
+    // a combination's tuple t, class ac and bin of every modulus of the tuple
+    // (residue identification); the class-list loads of a thread's next
+    // candidate are issued before its current one is processed
+    struct Combo {
+        int t, ac;
+        int32_t hg[kMaxG];
+    };
+    auto prep = [&](int c, Combo& cb) {
         int l0 = 0, h0 = nslots - 1;   // last slot with pre[slot] <= c
         while (l0 < h0) {
             const int mid = (l0 + h0 + 1) >> 1;
@@ -1824,125 +1821,149 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         }
         const int slot = l0;
         int r = c - pre[slot];
-        t = slot >> lg;
-        const int ac = slot & (s1 - 1);
-        // CRT without 64-bit divisions: every term is below M_t (a residue < m
-        // times M_t / m), so the sum is reduced by at most G subtractions
-        int64_t x = (int64_t)((ac * d->tup_inv[t][0]) & (s1 - 1)) * d->tup_Mi[t][0];
-        int32_t hg[kMaxG];   // the combination's bin of every modulus of the tuple (loads issued together)
+        cb.t = slot >> lg;
+        cb.ac = slot & (s1 - 1);
 #pragma unroll
         for (int g = 0; g < kMaxG; ++g) {
             if (g < G) {
-                const int jj = d->tup_j[t][g];
-                const int cg = ccount[(jj << lg) + ac];
+                const int jj = d->tup_j[cb.t][g];
+                const int cg = ccount[(jj << lg) + cb.ac];
                 const int ch = r % cg;
                 r /= cg;
-                hg[g] = CLall[(size_t)(jj * Q + b) * cl_stride + (size_t)ac * depth + ch];
+                cb.hg[g] = CLall[(size_t)(jj * Q + b) * cl_stride + (size_t)cb.ac * depth + ch];
             }
         }
-#pragma unroll
-        for (int g = 0; g < kMaxG; ++g) {
-            if (g < G) {
-                const uint32_t pm = (uint32_t)d->tup_mod[t][g + 1];
-                const uint32_t res = (uint32_t)hg[g] % pm;
-                x += (int64_t)((res * (uint32_t)d->tup_inv[t][g + 1]) % pm) * d->tup_Mi[t][g + 1];
-            }
-        }
-        const int64_t Mt = d->tup_M[t];
-        while (x >= Mt) x -= Mt;
-        if (x <= hi) w = x;
-        else if (x - Mt >= lo) w = x - Mt;
-        else continue;
-        }
-
-        // the bin of w in every modulus; the vote counts heavy bins among the
-        // moduli outside tuple t (a bin is heavy iff its key >= the block's
-        // threshold, i.e. iff it is in the block's heavy set)
-        int hh[kMaxK];
-        int votes = 0;
-        // residue identification: the vote is over the moduli outside tuple t;
-        // phase identification: over all K moduli
-        const int t_lo = (PHASE && phase) ? 0 : t * G, t_hi = (PHASE && phase) ? 0 : t_lo + G;
-        const int need = (PHASE && phase) ? K : K - G;
-        auto read_bins = [&](float* er, float* ei) {
-#pragma unroll
-            for (int jj = 0; jj < kMaxK; ++jj) {
-                if (jj < K) {
-                    const int Pj = d->P[jj];
-                    const int k2 = hh[jj] % d->p[jj];
-                    const float2 ev = ld2(Eall + (size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) +
-                                          (hh[jj] & (s1 - 1)));
-                    er[jj] = ev.x;
-                    ei[jj] = ev.y;
-                }
-            }
-        };
-#pragma unroll
-        for (int jj = 0; jj < kMaxK; ++jj) {
-            if (jj < K) {
-                if (small_n) {   // w fits 32 bits
-                    const int r32 = (int)w % d->P[jj];
-                    hh[jj] = r32 < 0 ? r32 + d->P[jj] : r32;
-                } else {
-                    hh[jj] = (int)pos_mod(w, d->P[jj]);
-                }
-            }
-        }
-        float er[kMaxK], ei[kMaxK];   // the K bin values, for the median
-        if constexpr (use_bm) {
-#pragma unroll
-            for (int jj = 0; jj < kMaxK; ++jj) {
-                if (jj < K) {
-                    const bool heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
-                    votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
-                }
-            }
-        } else {   // the same heavy test from the bin values: key >= the block's threshold
-            read_bins(er, ei);
-#pragma unroll
-            for (int jj = 0; jj < kMaxK; ++jj) {
-                if (jj < K) {
-                    const bool heavy = value_key(make_float2(er[jj], ei[jj]), (uint32_t)hh[jj]) >= sh_thr[jj];
-                    votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
-                }
-            }
-        }
-        if (2 * votes > need) {
-            if constexpr (use_bm) read_bins(er, ei);
+    };
+    // (the kernel that may also run phase identification loads each
+    // combination where it is used: it keeps fewer registers that way)
+    constexpr bool prefetch = !PHASE;
+    Combo cur, nxt;
+    if (prefetch && tid < total) prep(tid, cur);
+    for (int c = tid; c < total; c += kThreads) {
+        if (prefetch && c + kThreads < total) prep(c + kThreads, nxt);
+        {   // candidate c; a dropped candidate jumps to the end of the iteration
+            int64_t w;
+            int t = 0, jp = 0;   // CRT tuple (residue identification); producing modulus (phase)
             if (PHASE && phase) {
-                // one entry per frequency: an earlier modulus whose heavy bin at w
-                // gives w as well produces (and keeps) it
-                bool dup = false;
+                jp = c / T;
+                const int e = c - jp * T;
+                const int h0 = Hall[(size_t)(jp * Q + b) * T + e];
+                const size_t at0 = (size_t)Q * d->Moff[jp] + (size_t)b * d->P[jp] +
+                                   ((size_t)(h0 % d->p[jp]) << lg) + (size_t)(h0 & (s1 - 1));
+                if (!phase_frequency(ld2(Eall + at0), ld2(glb(io.E2) + at0), h0, d->P[jp], d->N, lo, hi, w)) goto next_candidate;
+            } else {
+            if constexpr (!prefetch) prep(c, cur);
+            t = cur.t;
+            const int ac = cur.ac;
+            // CRT without 64-bit divisions: every term is below M_t (a residue < m
+            // times M_t / m), so the sum is reduced by at most G subtractions
+            int64_t x = (int64_t)((ac * d->tup_inv[t][0]) & (s1 - 1)) * d->tup_Mi[t][0];
 #pragma unroll
-                for (int jj = 0; jj < kMaxK; ++jj) {   // compile-time indices: er, ei, hh stay in registers
-                    if (jj < jp && !dup) {
-                        const float2 ev = make_float2(er[jj], ei[jj]);
-                        bool heavy;
-                        if constexpr (use_bm) heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
-                        else heavy = value_key(ev, (uint32_t)hh[jj]) >= sh_thr[jj];
-                        if (heavy) {
-                            const size_t atj = (size_t)Q * d->Moff[jj] + (size_t)b * d->P[jj] +
-                                               ((size_t)(hh[jj] % d->p[jj]) << lg) + (size_t)(hh[jj] & (s1 - 1));
-                            int64_t w2;
-                            dup = phase_frequency(ev, ld2(glb(io.E2) + atj), hh[jj], d->P[jj], d->N, lo, hi, w2) &&
-                                  w2 == w;
-                        }
+            for (int g = 0; g < kMaxG; ++g) {
+                if (g < G) {
+                    const uint32_t pm = (uint32_t)d->tup_mod[t][g + 1];
+                    const uint32_t res = (uint32_t)cur.hg[g] % pm;
+                    x += (int64_t)((res * (uint32_t)d->tup_inv[t][g + 1]) % pm) * d->tup_Mi[t][g + 1];
+                }
+            }
+            const int64_t Mt = d->tup_M[t];
+            while (x >= Mt) x -= Mt;
+            if (x <= hi) w = x;
+            else if (x - Mt >= lo) w = x - Mt;
+            else goto next_candidate;
+            }
+
+            // the bin of w in every modulus; the vote counts heavy bins among the
+            // moduli outside tuple t (a bin is heavy iff its key >= the block's
+            // threshold, i.e. iff it is in the block's heavy set)
+            int hh[kMaxK];
+            int votes = 0;
+            // residue identification: the vote is over the moduli outside tuple t;
+            // phase identification: over all K moduli
+            const int t_lo = (PHASE && phase) ? 0 : t * G, t_hi = (PHASE && phase) ? 0 : t_lo + G;
+            const int need = (PHASE && phase) ? K : K - G;
+            auto read_bins = [&](float* er, float* ei) {
+#pragma unroll
+                for (int jj = 0; jj < kMaxK; ++jj) {
+                    if (jj < K) {
+                        const int Pj = d->P[jj];
+                        const int k2 = hh[jj] % d->p[jj];
+                        const float2 ev = ld2(Eall + (size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) +
+                                              (hh[jj] & (s1 - 1)));
+                        er[jj] = ev.x;
+                        ei[jj] = ev.y;
                     }
                 }
-                if (dup) continue;
+            };
+#pragma unroll
+            for (int jj = 0; jj < kMaxK; ++jj) {
+                if (jj < K) {
+                    if (small_n) {   // w fits 32 bits
+                        const int r32 = (int)w % d->P[jj];
+                        hh[jj] = r32 < 0 ? r32 + d->P[jj] : r32;
+                    } else {
+                        hh[jj] = (int)pos_mod(w, d->P[jj]);
+                    }
+                }
             }
-            const float zr = median_of(er, K);
-            const float zi = median_of(ei, K);
-            const float m2 = fmaf(zr, zr, zi * zi);
-            const int pos = atomicAdd(&sh_cnt, 1);
-            if (pos < acap) {
-                akey[pos] = ((uint64_t)__float_as_uint(m2) << 32) |
-                            (uint64_t)(0xffffffffu - (uint32_t)(w - lo));
-                az[pos] = make_float2(zr, zi);
-            } else {
-                atomicOr(io.status, kStatusAcceptOverflow);
+            float er[kMaxK], ei[kMaxK];   // the K bin values, for the median
+            if constexpr (use_bm) {
+#pragma unroll
+                for (int jj = 0; jj < kMaxK; ++jj) {
+                    if (jj < K) {
+                        const bool heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
+                        votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
+                    }
+                }
+            } else {   // the same heavy test from the bin values: key >= the block's threshold
+                read_bins(er, ei);
+#pragma unroll
+                for (int jj = 0; jj < kMaxK; ++jj) {
+                    if (jj < K) {
+                        const bool heavy = value_key(make_float2(er[jj], ei[jj]), (uint32_t)hh[jj]) >= sh_thr[jj];
+                        votes += (heavy && (jj < t_lo || jj >= t_hi)) ? 1 : 0;
+                    }
+                }
+            }
+            if (2 * votes > need) {
+                if constexpr (use_bm) read_bins(er, ei);
+                if (PHASE && phase) {
+                    // one entry per frequency: an earlier modulus whose heavy bin at w
+                    // gives w as well produces (and keeps) it
+                    bool dup = false;
+#pragma unroll
+                    for (int jj = 0; jj < kMaxK; ++jj) {   // compile-time indices: er, ei, hh stay in registers
+                        if (jj < jp && !dup) {
+                            const float2 ev = make_float2(er[jj], ei[jj]);
+                            bool heavy;
+                            if constexpr (use_bm) heavy = (bm[woff[jj] + (hh[jj] >> 5)] >> (hh[jj] & 31)) & 1u;
+                            else heavy = value_key(ev, (uint32_t)hh[jj]) >= sh_thr[jj];
+                            if (heavy) {
+                                const size_t atj = (size_t)Q * d->Moff[jj] + (size_t)b * d->P[jj] +
+                                                   ((size_t)(hh[jj] % d->p[jj]) << lg) + (size_t)(hh[jj] & (s1 - 1));
+                                int64_t w2;
+                                dup = phase_frequency(ev, ld2(glb(io.E2) + atj), hh[jj], d->P[jj], d->N, lo, hi, w2) &&
+                                      w2 == w;
+                            }
+                        }
+                    }
+                    if (dup) goto next_candidate;
+                }
+                const float zr = median_of(er, K);
+                const float zi = median_of(ei, K);
+                const float m2 = fmaf(zr, zr, zi * zi);
+                const int pos = atomicAdd(&sh_cnt, 1);
+                if (pos < acap) {
+                    akey[pos] = ((uint64_t)__float_as_uint(m2) << 32) |
+                                (uint64_t)(0xffffffffu - (uint32_t)(w - lo));
+                    az[pos] = make_float2(zr, zi);
+                } else {
+                    atomicOr(io.status, kStatusAcceptOverflow);
+                }
             }
         }
+    next_candidate:
+        if constexpr (prefetch) cur = nxt;
     }
     __syncthreads();
     const int nacc = min(sh_cnt, acap);
