@@ -138,8 +138,8 @@ def serving_runs(sft, siggen, torch, distinct: int = 256, arrivals: int = 1024,
     """The serving mix: requests with N uniform over 2^20..2^26, s log-uniform
     in [16, 1024], SNR uniform in [0, 40] dB (serving generator, seed 0).
     `distinct` inputs are generated and kept resident; the arrival stream
-    replays them in order.  Capacity = the requests of one saturated run (all
-    arriving at once) per second; then Poisson arrivals at each offered load
+    replays them in order.  Capacity = the requests per second of a saturated
+    run (all arriving at once; the median of three); then Poisson arrivals at each offered load
     (a fraction of that capacity), with p50/p99 arrival-to-result latency."""
     from paper_1706_02740_amd import serve
     spec = siggen.serving_requests(0, distinct, rate_hz=1.0)
@@ -166,7 +166,8 @@ def serving_runs(sft, siggen, torch, distinct: int = 256, arrivals: int = 1024,
                 "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}
 
     trace([0.0] * distinct)   # warm-up: arenas and kernels
-    sat = trace([0.0] * distinct)
+    sats = sorted((trace([0.0] * distinct) for _ in range(3)), key=lambda r: r["sft_per_s"])
+    sat = dict(sats[1], runs_sft_per_s=[r["sft_per_s"] for r in sats])   # the median of three saturated runs
     cap = sat["sft_per_s"]
     out = {"distinct_inputs": distinct, "plans": len(plans), "saturated": sat, "offered": {}}
     rng = np.random.Generator(np.random.PCG64(7))
