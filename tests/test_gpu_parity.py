@@ -383,3 +383,54 @@ def test_unfilled_slots_are_zero(gpu):
     assert 2 <= k <= s
     assert set(wn[:k].tolist()) >= set(sg.freqs.tolist())
     assert len(set(wn[:k].tolist())) == k
+
+
+def test_headline_launch_as_benchmarked(gpu):
+    """The headline in the launch configuration the benchmark times: 256
+    transforms per execute_many over 32 resident inputs.  Every output equals
+    the plain call on its input bit for bit; two inputs are also checked
+    against the oracle."""
+    N, s, B, distinct = 2 ** 22, 64, 256, 32
+    plan = gpu.Plan(N, s)
+    sigs = [siggen.workload("plain_n2e22_s64_20db", seed) for seed in range(distinct)]
+    fs = [dev(sg.f32) for sg in sigs]
+    say("headline batch of", B)
+    outs, counts = gpu.execute_many([plan] * B, [fs[i % distinct] for i in range(B)])
+    torch.cuda.synchronize()
+    plain = []
+    for f in fs:
+        w, c, n = plan.execute(f)
+        torch.cuda.synchronize()
+        k = int(n.item())
+        plain.append((w.cpu().numpy()[:k], c.cpu().numpy()[:k]))
+    for i in range(B):
+        k = int(counts[i].item())
+        wp, cp = plain[i % distinct]
+        assert np.array_equal(outs[i][0].cpu().numpy()[:k], wp), i
+        assert np.array_equal(outs[i][1].cpu().numpy()[:k], cp), i
+    op = _oplan(N, s, {})
+    for i in (5, 31):
+        wo, co = oracle.sft(op, sigs[i].f32)
+        assert_same_result(plain[i][0], plain[i][1], wo, co)
+
+
+def test_largest_serving_shape_n2e26_s1024(gpu):
+    """The largest request of the serving mix (N = 2^26, s = 1024, 30 dB;
+    512 MB of input, the split path with matrix-core columns).  Too large for
+    the oracle: checked against the known spectrum instead — the support is
+    exact and the coefficient error is at the noise level (per-coefficient
+    noise ~ sqrt(s) 10^(-30/20) / ghat-weighted band average; bound 1e-2)."""
+    N, s = 2 ** 26, 1024
+    say("largest serving shape", N, s)
+    plan = gpu.Plan(N, s)
+    assert plan.info["dft_path"] in (2, 4)
+    f, fr, co = siggen.sparse_signal_device(N, s, 11, 30.0)
+    w, c, n = plan.execute(f)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    k = int(n.item())
+    wg, cg = w.cpu().numpy()[:k], c.cpu().numpy()[:k]
+    truth = dict(zip(fr.tolist(), co))
+    assert set(wg.tolist()) == set(truth)
+    err = max(abs(complex(x) - truth[int(q)]) for q, x in zip(wg, cg))
+    assert err < 1e-2, err
