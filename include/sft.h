@@ -9,7 +9,7 @@
  * (Section 3.1, Lemma 10), runs short DFTs over those samples (Appendix B),
  * identifies energetic frequencies by residues, CRT and majority vote, and
  * estimates their coefficients by a median divided by ghat (Lemma 2), keeping
- * the s largest over all bands (Algorithm 1, line 16).
+ * the s largest over all bands (Algorithm 1, last step).
  *
  * Conventions
  *   - Frequencies are int64 integers in B = (-ceil(N/2), floor(N/2)]
@@ -60,7 +60,7 @@ extern "C" {
 #define SFT_PRESET_DMSFT4 1  /* kappa = 4 (9 taps); Section 5's DMSFT-4 window */
 #define SFT_PRESET_THEORY 2  /* beta = 6 sqrt(r), kappa = ceil(6 r ln N / (sqrt(2) pi)) + 1 (Theorem 4) */
 
-/* identification of the inner algorithm (Algorithm 1, line 9) */
+/* identification of the inner sparse FFT (Algorithm 1) */
 #define SFT_IDENT_RESIDUE 0  /* heavy bins of several moduli combined by the CRT, then a majority vote */
 #define SFT_IDENT_PHASE   1  /* each heavy bin's frequency from its phase against samples one grid step later */
 
@@ -108,7 +108,7 @@ typedef struct sft_params {
 } sft_params;
 
 /*
- * Every derived plan quantity (Algorithm 1, lines 2 and 4; Lemma 3;
+ * Every derived plan quantity (Algorithm 1's parameters and band centres; Lemma 3;
  * Theorem 4; the inner algorithm's moduli).  Band b = 0..Q-1 has centre
  * q_b = q_first + 2 b L and keeps the frequencies [q_b - L, q_b + L) of B.
  * Modulus j = 0..K-1 has short-DFT length P[j] = s1 * primes[j] and nodes
@@ -171,7 +171,7 @@ SFT_API int sft_plan_footprint(const sft_plan_t plan, size_t* bytes_device);
  * One transform, enqueued on stream (asynchronous, no host synchronisation).
  *   f_dev           complex64[N] on the device, read only.
  *   out_freqs_dev   int64[s]: frequencies ordered by |coefficient| descending,
- *                   ties to the smaller frequency (Algorithm 1, line 16).
+ *                   ties to the smaller frequency (Algorithm 1, last step).
  *   out_coeffs_dev  complex64[s]: the matching coefficients c_w.
  *   out_count_dev   int32[1] or NULL: number of filled slots n <= s; slots
  *                   n..s-1 hold w = 0, c = 0.

@@ -15,7 +15,7 @@ median reading of the inner algorithm (see ``oracle.sft``).  Everything is FP64 
 integers.
 
 Modules:
-  plan  -- parameter rules (Lemma 3, Algorithm 1 lines 2 and 4, Theorem 4)
+  plan  -- parameter rules (Lemma 3, Algorithm 1's parameters and band centres, Theorem 4)
   transform -- the transform itself, with every intermediate exposed
 """
 from .plan import (Params, Plan, make_plan, PRESET_DMSFT6, PRESET_DMSFT4,

@@ -12,7 +12,7 @@ Readings where the paper is silent (they are the same on both sides):
   Gaussian width in grid steps is sigma_t = sqrt((kappa + 1/2) / pi), which
   makes the window-truncation loss exp(-(kappa+1/2)^2 / (2 sigma_t^2)) equal
   to the aliasing loss exp(-(pi sigma_t)^2 / 2); then beta = 2 pi sigma_t /
-  sqrt(ln N) so that c1 = beta sqrt(ln N) / N (Algorithm 1, line 2).
+  sqrt(ln N) so that c1 = beta sqrt(ln N) / N (Algorithm 1's parameters).
 * preset ``theory``: beta = 6 sqrt(r), c1 = 6 sqrt(ln N^r) / N and the window
   half-width kappa = ceil(6 r ln N / (sqrt(2) pi)) + 1 of Theorem 4.
 * tau = 1/3 (the choice made after Lemma 13) and alpha taken at equality in
@@ -20,13 +20,13 @@ Readings where the paper is silent (they are the same on both sides):
   needs alpha in [1, N / sqrt(ln N)]; plans outside that range are rejected
   (for dmsft6 this means N >= 31).
 * c2 = alpha sqrt(ln N) / 2, Q = ceil(c2) bands, L = ceil(N / (alpha sqrt(ln N)))
-  and q_b = -ceil(N/2) + 1 + (2b - 1) L (Algorithm 1, lines 2 and 4).
+  and q_b = -ceil(N/2) + 1 + (2b - 1) L (Algorithm 1's parameters and band centres).
 * inner algorithm: moduli P_j = s1 * p_j with s1 the least power of two
   >= 2 s (times an optional multiplier), G = max(2, ceil(log2(N / s1) / 6)),
   p_min the least integer with p_min^G * s1 >= N, and p_1 < ... < p_K the
   K = 2G + 1 smallest odd primes >= max(3, p_min).  Two CRT tuples of G
   moduli each: (1..G) and (G+1..2G).  T = min(2 s, P_1) heavy bins per DFT.
-* identification (line 9's inner algorithm): ``IDENT_RESIDUE`` combines heavy
+* identification (the inner sparse FFT of Algorithm 1): ``IDENT_RESIDUE`` combines heavy
   bins of several moduli by the CRT; ``IDENT_PHASE`` reads each heavy bin's
   frequency from the phase between the bin and the same bin of samples taken
   one grid step later (the phase-shift family the paper pairs with CLW-DSFT in

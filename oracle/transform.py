@@ -2,8 +2,8 @@
 
 Algorithm 1 (Section 3), step by step, in FP64 and exact integers:
 
-for each band b = 1..Q (Algorithm 1, lines 3-4):
-  1. filtered samples (line 7): at every node theta = 2 pi k / P_j of every
+for each band b = 1..Q (Algorithm 1's loop over the band centres):
+  1. filtered samples (Algorithm 1's convolution step): at every node theta = 2 pi k / P_j of every
      modulus j, evaluate the truncated semi-discrete convolution of Lemma 10,
          S_b(theta) = sum_{i=-kappa..kappa} f[(j'+i) mod N] * W(u - i)
                                           * exp(2 pi i q_b (u - i) / N),
@@ -11,8 +11,8 @@ for each band b = 1..Q (Algorithm 1, lines 3-4):
      (ties rounded up), u = t - j', and W(v) = g(2 pi v / N) / N is the
      periodized Gaussian of eq. (Def_Periodic_Gaussian) with c1 from the plan.
      The modulation is g~_q(x) = exp(+i q x) g(x), whose Fourier coefficients
-     are ghat_{w-q}; this is the sign under which the band test of line 10 and
-     the division of line 11 keep and rescale the frequencies near +q.
+     are ghat_{w-q}; this is the sign under which Algorithm 1's band test and
+     its division keep and rescale the frequencies near +q.
   2. short DFTs (Appendix B, eq. DFT_GKlam_Comp):
          E_b[j][h] = (1/P_j) sum_k S_b(2 pi k / P_j) exp(-2 pi i k h / P_j).
   3. heavy bins: the T bins of largest |E_b[j][h]|^2, ties to the lower h.
@@ -25,10 +25,10 @@ for each band b = 1..Q (Algorithm 1, lines 3-4):
      vote is taken over the other K - G moduli: keep w if more than half of
      them have (w mod P_j) among their heavy bins (for some producing tuple).
   6. estimate: z_w = median_j Re E_b[j][w mod P_j] + i median_j Im(...).
-  7. line 9: the s largest |z_w| (ties to the smaller w) form R_temp.
-  8. lines 10-11: keep w in [q_b - L, q_b + L) and B; divide by
+  7. the inner algorithm's output: the s largest |z_w| (ties to the smaller w) form R_temp.
+  8. band test and division: keep w in [q_b - L, q_b + L) and B; divide by
      ghat_{w - q_b} = exp(-c1^2 (w - q_b)^2 / 2) / sqrt(2 pi) (Lemma 2).
-then (line 16) return the s largest |v_w| over all bands, ties to the smaller w.
+then (Algorithm 1's last step) return the s largest |v_w| over all bands, ties to the smaller w.
 
 Phase identification (plan.ident == IDENT_PHASE) replaces steps 4-5:
   1'. the samples of step 1 are also taken at every node moved one grid step,
@@ -97,7 +97,7 @@ def ghat(plan: Plan, n) -> np.ndarray:
 
 
 def filtered_samples(plan: Plan, f: np.ndarray, b: int, j: int, shift: int = 0) -> np.ndarray:
-    """S_b at the nodes of modulus j (Algorithm 1, line 7; Lemma 10's window).
+    """S_b at the nodes of modulus j (Algorithm 1's convolution step; Lemma 10's window).
 
     shift moves every node by that many grid steps (theta + 2 pi shift / N):
     the nearest grid index moves with it and the offset u does not, so the
@@ -262,9 +262,9 @@ def _band(plan: Plan, f: np.ndarray, b: int, keep: bool):
         for w, tuples in cands.items():
             if accepted_by_vote(plan, heavy_sets, w, tuples):
                 accepted.append((w, median_estimate(plan, E, w)))
-    # Algorithm 1, line 9: the s-sparse output of the inner algorithm
+    # the s-sparse output of the inner algorithm (Algorithm 1)
     r_temp = sorted(accepted, key=lambda wz: (-abs(wz[1]), wz[0]))[: plan.s]
-    # lines 10-11: band test and division by the modulated filter's coefficient
+    # band test and division by the modulated filter's coefficient (Algorithm 1)
     q = plan.q[b]
     out = []
     for w, z in r_temp:

@@ -1,18 +1,23 @@
 // HIP kernels of the sparse Fourier transform hot path (gfx950, wave64).
 //
-//   k_gather    filtered samples S_b(x_k) for every node and band  (Algorithm 1, line 7;
+//   k_gather    filtered samples S_b(x_k) for every node and band  (Algorithm 1, convolution step;
 //               Section 3.1, Lemma 10's 2 kappa + 1 nearest grid values)
-//   k_dft       short DFTs of length P_j = s1 p_j (Appendix B) by Good-Thomas:
-//               radix-2 over s1 in LDS, direct p-point over the prime, then the
-//               top-T bins by |E|^2 (radix select), bucketed by residue class mod s1
-//   k_identify  CRT candidates per residue class, majority vote over the K moduli,
-//               componentwise median, per-band s-term, band test, division by ghat
-//               (Algorithm 1, lines 9-11; Appendix B)
-//   k_merge     global s-term over the bands (Algorithm 1, line 16)
+//   k_dft       short DFTs of length P_j = s1 p_j (Appendix B) by Good-Thomas, a
+//               whole block in LDS: s1-point row FFTs, the p-point step on the
+//               matrix cores (k_dft<0, true>) or the vector ALUs, then the top-T
+//               bins by |E|^2 (radix select), bucketed by residue class mod s1
+//   k_dft_rows, k_dft_cols, k_dft_cols_mx, k_select
+//               the same for blocks larger than the LDS, in three steps over HBM
+//   k_identify  candidates per residue class (CRT) or from bin phases, majority
+//               vote, componentwise median, per-band s-term, band test, division
+//               by ghat (Algorithm 1: inner sparse FFT, band test, division; Appendix B)
+//   k_merge     global s-term over the bands (Algorithm 1, last step)
 //
-// Every kernel runs 256-thread workgroups.  A launch covers one transform
-// (BatchArgs::descs_many == nullptr) or a batch, where a per-signal block
-// prefix maps blockIdx.x to (signal, local block).
+// Workgroups have 256 threads, except k_dft and k_dft_cols_mx (512) and the
+// LDS-key form of k_select (1024).  A launch covers one transform
+// (BatchArgs::io_many == nullptr) or a batch, where a per-signal block prefix
+// (or, for a batch of one plan, a division) maps blockIdx.x to (signal, local
+// block).
 #include <algorithm>
 
 #include "sft_internal.h"

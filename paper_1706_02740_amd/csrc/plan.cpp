@@ -1,7 +1,7 @@
 // Host-side plan rules: FP64 constants and exact integer searches.
 //
-//   c1 = beta sqrt(ln N) / N, c2 = alpha sqrt(ln N) / 2           (Algorithm 1, line 2)
-//   q_b = -ceil(N/2) + 1 + (2b - 1) ceil(N / (alpha sqrt(ln N)))    (Algorithm 1, line 4)
+//   c1 = beta sqrt(ln N) / N, c2 = alpha sqrt(ln N) / 2           (Algorithm 1, parameters)
+//   q_b = -ceil(N/2) + 1 + (2b - 1) ceil(N / (alpha sqrt(ln N)))    (Algorithm 1, band centres)
 //   alpha at equality in Lemma 3, tau = 1/3 by default (after Lemma 13)
 //   theory preset: beta = 6 sqrt(r), kappa = ceil(6 r ln N / (sqrt(2) pi)) + 1 (Theorem 4)
 //   dmsft presets: kappa = 6 or 4 (Section 5), sigma_t = sqrt((kappa + 1/2) / pi) in grid

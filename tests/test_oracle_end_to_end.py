@@ -123,7 +123,7 @@ def test_linearity_disjoint_supports():
 
 def test_band_edge_frequencies():
     """Frequencies on the edges of the bands [q_b - L, q_b + L) and of B are
-    found exactly once (Algorithm 1, line 10, with B's convention)."""
+    found exactly once (Algorithm 1's band test, with B's convention)."""
     N = 2 ** 14
     plan = make_plan(N, 12)
     lo, hi = siggen.band_limits(N)

@@ -306,7 +306,7 @@ def test_plan_invariants(N, s, preset):
     p = make_plan(N, s, Params(preset=preset))
     # Lemma 3: the passband |w| <= L keeps ghat >= tau
     assert float(oracle.ghat(p, p.L)) >= p.tau
-    # bands [q_b - L, q_b + L) are disjoint and cover B (Algorithm 1, lines 3-4 and 10)
+    # bands [q_b - L, q_b + L) are disjoint and cover B (Algorithm 1's band centres and band test)
     edges = [(q - p.L, q + p.L) for q in p.q]
     assert edges[0][0] == p.band_lo
     for a, b in zip(edges, edges[1:]):
