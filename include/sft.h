@@ -139,6 +139,9 @@ typedef struct sft_plan_info {
     int32_t dft_path;   /* short-DFT path the plan runs (1-4; 0 from sft_plan_describe) */
     int64_t P[SFT_MAX_MODULI];
     int64_t M;          /* sum of P[j]: nodes per band */
+    int32_t dft_split;  /* dft_path 3: the moduli [0, dft_split) run as a launch of their own with a
+                           smaller LDS allocation per workgroup (more workgroups per CU); 0: one
+                           launch (always 0 from sft_plan_describe) */
 } sft_plan_info;
 
 typedef struct sft_plan_s* sft_plan_t;

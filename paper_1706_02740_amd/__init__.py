@@ -91,7 +91,7 @@ class PlanInfo(ctypes.Structure):
                 ("c1", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("c2", ctypes.c_double), ("r", ctypes.c_double),
                 ("primes", ctypes.c_int32 * MAX_MODULI), ("dft_path", ctypes.c_int32),
-                ("P", ctypes.c_int64 * MAX_MODULI), ("M", ctypes.c_int64)]
+                ("P", ctypes.c_int64 * MAX_MODULI), ("M", ctypes.c_int64), ("dft_split", ctypes.c_int32)]
 
 
 _lib = None

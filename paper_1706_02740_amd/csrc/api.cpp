@@ -44,6 +44,7 @@ struct sft_plan_s {
     size_t lds[SFT_KERNEL_COUNT] = {};
     int blocks[SFT_KERNEL_COUNT] = {};   // per transform; 0 = kernel not used
     bool split = false;     // short DFTs too large for one workgroup's LDS
+    MxSplit mxs;            // the matrix-core short DFTs in two launches (mxs.j1 > 0)
     int device = 0;
     hipStream_t last_stream = nullptr;
 };
@@ -135,7 +136,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     }
     const bool fits = dft_fits_one_workgroup(d) && dft_lds_bytes(d) <= lds_cap;
     const int mx = dft_mfma_variant(d);
-    const bool mx_fits = mx != 0 && dft_lds_bytes(d) <= lds_cap;
+    const bool mx_fits = mx != 0 && dft_mx_lds_bytes(d, d.K) <= lds_cap;
     if (path == 1 && !fits) {
         delete pl;
         return fail(SFT_EUNSUPPORTED, "the in-LDS short-DFT kernel cannot hold this plan (use dft_path 0 or 2)");
@@ -168,8 +169,25 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     if (!pl->split) {
         const bool use_mx = path == 3 || (path == 0 && mx_fits);
         if (use_mx) {
-            pl->lds[SFT_KERNEL_DFT_MX] = dft_lds_bytes(d);
+            pl->lds[SFT_KERNEL_DFT_MX] = dft_mx_lds_bytes(d, d.K);
             pl->blocks[SFT_KERNEL_DFT_MX] = dft_blocks(d);
+            // Two workgroups of the largest blocks fill a CU's LDS; when the
+            // smaller moduli's blocks fit three to a CU, they get a launch of
+            // their own with that smaller allocation (measured: three
+            // workgroups per CU take ~20 % less time per block than two).
+            // The margin covers the static LDS and the allocation granularity.
+            const size_t third = (size_t)lds_limit / 3 - 512;
+            if (pl->lds[SFT_KERNEL_DFT_MX] > third) {
+                int j1 = 0;
+                while (j1 < d.K && dft_mx_lds_bytes(d, j1 + 1) <= third) ++j1;
+                if (j1 > 0 && j1 < d.K) {
+                    pl->mxs.j1 = j1;
+                    pl->mxs.K = d.K;
+                    pl->mxs.qb = d.Q * (1 + d.phase);
+                    pl->mxs.lds_lo = dft_mx_lds_bytes(d, j1);
+                }
+            }
+            pl->info.dft_split = pl->mxs.j1;
         } else {
             // low 32 bits: LDS bytes; above: output pairs per thread (selects the kernel variant)
             pl->lds[SFT_KERNEL_DFT] = dft_lds_bytes(d) | ((size_t)dft_pairs_per_thread(d) << 32);
@@ -425,16 +443,35 @@ LaunchFn launcher(int k) {
 // batch; both null for a single transform.
 // timing: per-kernel HIP events when profiling is on (off while a graph is
 // captured).
+// mxs: the plan's split of the matrix-core short DFTs (single transforms and
+// one-plan batches; null for a batch of several plans, whose block prefix
+// covers every modulus).
 int enqueue(BatchArgs a, const int blocks[SFT_KERNEL_COUNT], const size_t lds[SFT_KERNEL_COUNT],
-            const int32_t* const prefix[SFT_KERNEL_COUNT], hipStream_t st, const int* bps, bool timing = true) {
+            const int32_t* const prefix[SFT_KERNEL_COUNT], hipStream_t st, const int* bps, const MxSplit* mxs,
+            bool timing = true) {
     for (int o = 0; o < SFT_KERNEL_COUNT; ++o) {
         const int k = kOrder[o];
         if (blocks[k] <= 0) continue;
         a.prefix = prefix ? prefix[k] : nullptr;
         a.bps = bps ? bps[k] : 0;
         LaunchFn fn = launcher(k);
-        const hipError_t e = timing ? timed(k, st, [&] { return fn(a, blocks[k], lds[k], st); })
-                                    : fn(a, blocks[k], lds[k], st);
+        auto launch = [&]() -> hipError_t {
+            if (k != SFT_KERNEL_DFT_MX || !mxs || mxs->j1 <= 0 || prefix) return fn(a, blocks[k], lds[k], st);
+            // moduli [0, j1) with the smaller LDS allocation, then [j1, K)
+            const int per = mxs->K * mxs->qb;
+            const int count = blocks[k] / per;
+            BatchArgs b = a;
+            b.jlo = 0;
+            b.jn = mxs->j1;
+            b.bps = bps ? mxs->j1 * mxs->qb : 0;
+            hipError_t e = fn(b, count * mxs->j1 * mxs->qb, mxs->lds_lo, st);
+            if (e != hipSuccess) return e;
+            b.jlo = mxs->j1;
+            b.jn = mxs->K - mxs->j1;
+            b.bps = bps ? (mxs->K - mxs->j1) * mxs->qb : 0;
+            return fn(b, count * (mxs->K - mxs->j1) * mxs->qb, lds[k], st);
+        };
+        const hipError_t e = timing ? timed(k, st, launch) : launch();
         if (e != hipSuccess) return hip_fail(e, kNames[k]);
     }
     return SFT_OK;
@@ -527,13 +564,13 @@ int enqueue_batch(const BatchShape& B, const sft_plan_t* plans, int32_t count, c
     a.nsig = count;
     if (B.one_plan) {   // blocks follow from blockIdx by a division; one descriptor
         a.desc_one = plans[0]->ddesc;
-        return enqueue(a, blocks, B.lds, nullptr, st, plans[0]->blocks, timing);
+        return enqueue(a, blocks, B.lds, nullptr, st, plans[0]->blocks, &plans[0]->mxs, timing);
     }
     a.descs_many = reinterpret_cast<const SigDesc* const*>(dm);
     const int32_t* dpre[SFT_KERNEL_COUNT];
     for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
         dpre[k] = reinterpret_cast<const int32_t*>(dm + B.m_desc + B.m_io + k * B.m_pre);
-    return enqueue(a, blocks, B.lds, dpre, st, nullptr, timing);
+    return enqueue(a, blocks, B.lds, dpre, st, nullptr, nullptr, timing);
 }
 
 // ----------------------------------------------------- batch arenas ----
@@ -604,7 +641,7 @@ int sft_execute(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_dev, void
     a.io_one.out_n = out_count_dev;
     a.nsig = 1;
     plan->last_stream = st;
-    return enqueue(a, plan->blocks, plan->lds, nullptr, st, nullptr);
+    return enqueue(a, plan->blocks, plan->lds, nullptr, st, nullptr, &plan->mxs);
 }
 
 int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* f_dev,

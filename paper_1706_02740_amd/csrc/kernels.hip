@@ -17,7 +17,7 @@
 // LDS-key form of k_select (1024).  A launch covers one transform
 // (BatchArgs::io_many == nullptr) or a batch, where a per-signal block prefix
 // (or, for a batch of one plan, a division) maps blockIdx.x to (signal, local
-// block).
+// block).  A k_dft launch may cover a range of the moduli only.
 #include <algorithm>
 
 #include "sft_internal.h"
@@ -1010,11 +1010,16 @@ __device__ __forceinline__ float lane_pair(float v) {
 // receives D[4 (l / 16) + r][l % 16] in register r.  Wave w owns the N-tiles
 // w + 8 t (t < ntw = s1 / 64) and the M-tiles m < mt = ceil((h + 1) / 16)
 // (at most NTW and MT).  bf: the block as floats.
-// At: the A operands in lane order ((st kMxTiles + m) 64 + lane, as the
-// plan's mxa table), in LDS.
-template <int MT, int NTW, int ATILES = kMxTiles>
-__device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, int mt, int ntw, const float2* At,
-                                         mf4 (&Cm)[NTW][MT], mf4 (&Dm)[NTW][MT]) {
+// At: the A operands in lane order ((st ATILES + m) 64 + lane, as the
+// plan's mxa and mxc tables), in LDS or global memory; an: on entry the
+// operands of step 0 (At[m 64 + lane]); each step's operands are loaded one
+// step ahead.
+__device__ __forceinline__ float2 load_a(const float2* p) { return *p; }
+__device__ __forceinline__ float2 load_a(const GLOBAL float2* p) { return ld2(p); }
+
+template <int MT, int NTW, int ATILES = kMxTiles, class AP>
+__device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, int mt, int ntw, AP At,
+                                         float2 (&an)[MT], mf4 (&Cm)[NTW][MT], mf4 (&Dm)[NTW][MT]) {
     static_assert(MT <= ATILES, "A operand tiles");
     const int lane = (int)threadIdx.x & 63;
     const int wid = (int)threadIdx.x >> 6;
@@ -1034,7 +1039,11 @@ __device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, 
         const bool nin = n <= h;
         float2 av[MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) av[m] = At[(st * ATILES + m) * 64 + lane];
+        for (int m = 0; m < MT; ++m) av[m] = an[m];
+        if (st + 1 < steps) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m) an[m] = load_a(At + ((st + 1) * ATILES + m) * 64 + lane);
+        }
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             if (t >= ntw) break;
@@ -1078,7 +1087,11 @@ struct MfmaClassThreads {
 // MX: step B on the matrix cores (pfa_mfma, up to MT = NTW = 2).  Requires
 // s1 = 64 or 128 and h + 1 <= 32 for every modulus.  Slot (t MT + m) 4 + r
 // holds the key of row k = 16 m + 4 (l / 16) + r of N-tile w + 8 t: X_k in
-// even lanes, X_{p-k} in odd lanes (row 0 in even lanes only).
+// even lanes, X_{p-k} in odd lanes (row 0 in even lanes only).  LDS: the block
+// and the s1 twiddles only (the A operands come from the plan's table in
+// global memory); the selection's scratch reuses the block's space, so a
+// launch over the smaller moduli (BatchArgs::jn) needs less LDS per
+// workgroup and fits more workgroups per CU.
 template <int KBMAX, bool MX>
 __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     constexpr int MT = MX ? 2 : 0;
@@ -1091,45 +1104,52 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const int tid = (int)threadIdx.x;
     const int Q = d->Q;
     const int K = d->K;
-    // blocks K Q .. 2 K Q - 1 (phase identification): the bins of the samples
+    // A launch may cover the moduli [jlo, jlo + nj) only (jn > 0), so that
+    // the smaller blocks get a smaller LDS allocation and more workgroups per CU.
+    const int jlo = a.jn > 0 ? a.jlo : 0;
+    const int nj = a.jn > 0 ? a.jn : K;
+    // blocks nj Q .. 2 nj Q - 1 (phase identification): the bins of the samples
     // at the nodes moved one grid step, transformed and stored only
-    const bool shifted = at.blk >= K * Q;
-    const int blk0 = shifted ? at.blk - K * Q : at.blk;
-    const int j = blk0 / Q;
-    const int b = blk0 - j * Q;
+    const bool shifted = at.blk >= nj * Q;
+    const int blk0 = shifted ? at.blk - nj * Q : at.blk;
+    const int j = jlo + blk0 / Q;
+    const int b = blk0 - (j - jlo) * Q;
     const int p = d->p[j];
     const int P = d->P[j];
     const int s1 = d->s1;
     const int lg = d->log2s1;
-    const int Pmax = d->P[K - 1];
-    const int hmax = (d->p[K - 1] - 1) >> 1;
+    const int Pmax = d->P[jlo + nj - 1];   // the moduli ascend
+    const int hmax = (d->p[jlo + nj - 1] - 1) >> 1;
     const int h = (p - 1) >> 1;
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
 
     float2* buf = reinterpret_cast<float2*>(smem);
     float2* tw = reinterpret_cast<float2*>(smem + (size_t)Pmax * 8);   // [s1]
-    float2* trig = tw + s1;
-    int32_t* hist = reinterpret_cast<int32_t*>(trig + hmax * hmax);
+    float2* trig = tw + s1;   // VALU step B: the cosine/sine table [hmax^2]
+    // selection scratch: after the table (VALU step B), or over the block
+    // once step B has read it (MX)
+    int32_t* hist = MX ? reinterpret_cast<int32_t*>(smem) : reinterpret_cast<int32_t*>(trig + hmax * hmax);
     int32_t* part = hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [T]
     int32_t* cl = reinterpret_cast<int32_t*>(hk + d->T);        // [s1 depth]
 
     const GLOBAL float2* __restrict__ S = glb(shifted ? io.S2 : io.S) + base;
+    constexpr int MTA = MX ? 2 : 1;
+    const GLOBAL float2* A = glb(d->mxa) + (size_t)j * kMxSteps * kMxTiles * 64;   // MX: [step][tile][lane]
+    float2 a0[MTA];   // MX: the A operands of step B's first K-step
     if constexpr (MX) {
         // every load of the block in flight at once: samples, twiddles, the
-        // p-point step's A operands (to LDS in place of the cosine/sine table)
-        static_assert(kMxSteps * kMxTiles * 64 == 2 * NT, "two A operands per thread");
+        // first A operands of the p-point step (the others are read from the
+        // plan's table, one K-step ahead, as the step runs)
         float2 w = make_float2(0.f, 0.f);
         if (tid < (s1 >> 1)) w = ld2(glb(d->tw_s1) + tid);
-        const GLOBAL float2* A = glb(d->mxa) + (size_t)j * kMxSteps * kMxTiles * 64;
-        const float2 a0 = ld2(A + tid), a1 = ld2(A + tid + NT);
+#pragma unroll
+        for (int m = 0; m < MTA; ++m) a0[m] = ld2(A + m * 64 + (tid & 63));
         copy_to_lds<NT, 8>(buf, S, P);
         if (tid < (s1 >> 1)) {   // the full circle: W^(m + s1/2) = -W^m
             tw[tid] = w;
             tw[tid + (s1 >> 1)] = make_float2(-w.x, -w.y);
         }
-        trig[tid] = a0;
-        trig[tid + NT] = a1;
     } else {
         copy_to_lds<NT, 8>(buf, S, P);
         for (int i = tid; i < (s1 >> 1); i += NT) {   // the full circle: W^(m + s1/2) = -W^m
@@ -1160,7 +1180,8 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         const float* bf = reinterpret_cast<const float*>(buf);
         const int mt = (h + 16) >> 4;
         const int ntw = s1 >> 6;
-        pfa_mfma<MT, NTW>(bf, s1, p, h, mt, ntw, trig, Cm, Dm);
+        static_assert(MT == MTA, "first A operands");
+        pfa_mfma<MT, NTW>(bf, s1, p, h, mt, ntw, A, a0, Cm, Dm);
         const float sgn = plane ? -1.f : 1.f;
 #pragma unroll
         for (int q = 0; q < NK; ++q) hi[q] = 0;
@@ -1230,6 +1251,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     }
     }
     if (shifted) return;   // uniform over the block
+    if constexpr (MX) __syncthreads();   // the selection's scratch overlays the block, which step B has read
     // Good-Thomas position of slot q of thread th
     auto pos_of = [&](int q, int th) -> int {
         if constexpr (MT > 0) {
@@ -1429,7 +1451,10 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
     mf4 Cm[1][MT], Dm[1][MT];
     const float* bf = reinterpret_cast<const float*>(tile);
     const int mt = (h + 16) >> 4;
-    pfa_mfma<MT, 1, kMxcTiles>(bf, C, p, h, mt, 1, At, Cm, Dm);
+    float2 a0[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) a0[m] = At[m * 64 + (tid & 63)];
+    pfa_mfma<MT, 1, kMxcTiles>(bf, C, p, h, mt, 1, static_cast<const float2*>(At), a0, Cm, Dm);
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int li = lane & 15;

@@ -238,12 +238,21 @@ size_t dft_lds_bytes(const SigDesc& d) {
     for (int j = 0; j < d.K; ++j)
         if (d.P[j] > Pmax) Pmax = d.P[j];
     const size_t h = (size_t)(d.p[d.K - 1] - 1) / 2;
-    // the cosine/sine table, or the matrix-core step's A operands
-    const size_t ntrig = dft_mfma_variant(d) ? std::max(h * h, (size_t)kMxSteps * kMxTiles * 64) : h * h;
-    // data (8 B per bin) + s1 twiddles + the table + histogram + scan partials
-    // + the T heavy keys + the class lists
+    // data (8 B per bin) + s1 twiddles + the cosine/sine table + histogram +
+    // scan partials + the T heavy keys + the class lists (the VALU step B;
+    // dft_mx_lds_bytes gives the matrix-core kernel's)
+    const size_t ntrig = h * h;
     return (size_t)Pmax * 8 + (size_t)d.s1 * 8 + ntrig * 8 + (size_t)kSelBins * 4 + 64 + (size_t)d.T * 8 +
            (size_t)d.s1 * d.depth * 4 + 64;
+}
+
+size_t dft_mx_lds_bytes(const SigDesc& d, int jhi) {
+    // the block (8 B per bin) and the s1 twiddles; once step B has read the
+    // block, the selection's histogram, scan partials, T heavy keys and class
+    // lists take its place
+    const size_t block = (size_t)d.P[jhi - 1] * 8 + (size_t)d.s1 * 8;
+    const size_t scratch = (size_t)kSelBins * 4 + 64 + (size_t)d.T * 8 + (size_t)d.s1 * d.depth * 4;
+    return std::max(block, scratch) + 64;
 }
 
 int dft_pairs_per_thread(const SigDesc& d) {

@@ -109,6 +109,15 @@ struct BatchArgs {
     const int32_t* prefix;             // [nsig+1] first block of each signal for this kernel (mixed)
     int32_t nsig;
     int32_t bps;                       // blocks per transform of a one-plan batch, else 0
+    int32_t jlo, jn;                   // short-DFT launches: the moduli [jlo, jlo + jn) only (jn = 0: all)
+};
+
+// The matrix-core short DFTs of a plan in two launches: moduli [0, j1) with
+// lds_lo bytes per workgroup, then [j1, K) (j1 = 0: one launch).  qb: blocks
+// per modulus of one transform, Q (1 + phase).
+struct MxSplit {
+    int j1 = 0, K = 0, qb = 0;
+    size_t lds_lo = 0;
 };
 
 // Per-signal workspace sizes in bytes (each slice 256-byte aligned).
@@ -121,6 +130,8 @@ int derive_plan(int64_t N, int32_t s, const sft_params* p, sft_plan_info* out, c
 void fill_desc(const sft_plan_info& info, SigDesc* d);
 WorkspaceLayout workspace_layout(const sft_plan_info& info);
 size_t dft_lds_bytes(const SigDesc& d);
+// LDS of the matrix-core in-LDS short-DFT kernel for a launch over the moduli [0, jhi) or up to jhi.
+size_t dft_mx_lds_bytes(const SigDesc& d, int jhi);
 bool dft_fits_one_workgroup(const SigDesc& d);   // the in-LDS short-DFT kernel's shape limits
 int dft_pairs_per_thread(const SigDesc& d);
 // Whether the in-LDS kernel's matrix-core step B covers the plan (s1 = 64 NTW, h + 1 <= 16 MT, NTW, MT <= 2):

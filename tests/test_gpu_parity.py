@@ -308,17 +308,22 @@ def test_split_dft_path_equals_in_lds_path(gpu, N, s, snr, kw):
 
 
 @pytest.mark.parametrize("N,s,snr,kw", [(2 ** 16, 40, 10.0, {}), (100_003, 20, 20.0, {}),
-                                        (2 ** 14, 32, None, {"ident": "phase"})])
+                                        (2 ** 14, 32, None, {"ident": "phase"}),
+                                        (2 ** 22, 64, 20.0, {}), (2 ** 22, 64, 20.0, {"ident": "phase"})])
 def test_split_matrix_core_path_equals_in_lds_matrix_core_path(gpu, N, s, snr, kw):
     """The split path with matrix-core columns performs the p-point step with
     the same operands in the same order as the in-LDS matrix-core kernel:
-    bins, heavy sets and outputs are bitwise equal."""
+    bins, heavy sets and outputs are bitwise equal.  At N = 2^22, s = 64 the
+    in-LDS kernel runs as two launches (the smaller moduli with a smaller LDS
+    allocation), for both identifications."""
     say("split mx vs lds mx", N, s, kw)
     sg = siggen.sparse_signal(N, s, seed=21, snr_db=snr)
     f = dev(sg.f32)
     res = []
     for path in (3, 4):
         plan = gpu.Plan(N, s, dft_path=path, **kw)
+        if path == 3 and N == 2 ** 22:
+            assert 0 < plan.info["dft_split"] < plan.info["K"]
         w, c, n = plan.execute(f)
         torch.cuda.synchronize()
         res.append((w.cpu().numpy(), c.cpu().numpy(), plan.fetch(gpu.FETCH_BINS), plan.fetch(gpu.FETCH_HEAVY)))
@@ -434,3 +439,19 @@ def test_largest_serving_shape_n2e26_s1024(gpu):
     assert set(wg.tolist()) == set(truth)
     err = max(abs(complex(x) - truth[int(q)]) for q, x in zip(wg, cg))
     assert err < 1e-2, err
+
+
+def test_matrix_core_moduli_split_rule(gpu):
+    """The in-LDS matrix-core kernel is split into two launches exactly when
+    its largest block leaves room for only two workgroups per CU and the
+    smaller moduli's blocks fit three: N = 2^22, s = 64 (blocks of 37..61
+    columns of 128 bins) splits after the moduli up to 47; N = 2^21, s = 32
+    (64 bins per row) runs as one launch; split path plans report 0."""
+    head = gpu.Plan(2 ** 22, 64)
+    assert head.info["dft_path"] == 3
+    primes = head.info["primes"]
+    j1 = head.info["dft_split"]
+    assert 0 < j1 < head.info["K"]
+    assert max(primes[:j1]) < min(primes[j1:]) and primes[j1 - 1] == 47
+    assert gpu.Plan(2 ** 21, 32, dft_path=3).info["dft_split"] == 0
+    assert gpu.Plan(2 ** 22, 64, dft_path=4).info["dft_split"] == 0
