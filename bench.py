@@ -475,7 +475,9 @@ def main():
                 "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None,
                 "traffic_detail": tr,
                 "algorithmic_bytes_per_launch": byts * tpl[dom], "avg_launch_ms": kern[dom]["avg_ms"],
-                "transforms_per_launch": tpl[dom]}
+                "transforms_per_launch": tpl[dom],
+                # a k_dft_mx launch of a split plan is two dispatches (smaller moduli, then the rest)
+                "dispatches_per_launch": 2 if dom == "k_dft_mx" and info.get("dft_split") else 1}
     gb = per_kernel.get("k_gather", {}).get("GBps", 0.0)
 
     # ---- accuracy against the oracle outputs of the CPU baseline

@@ -122,6 +122,8 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     int lds_limit = 0;
     if ((rc = device_lds_limit(dev, &lds_limit)) != SFT_OK) return rc;
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
 
     sft_plan_s* pl = new sft_plan_s();
     pl->info = info;
@@ -181,6 +183,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
                 int j1 = 0;
                 while (j1 < d.K && dft_mx_lds_bytes(d, j1 + 1) <= third) ++j1;
                 if (j1 > 0 && j1 < d.K) {
+                    pl->mxs.min_blocks = 12 * cus;   // four rounds of three workgroups per CU
                     pl->mxs.j1 = j1;
                     pl->mxs.K = d.K;
                     pl->mxs.qb = d.Q * (1 + d.phase);
@@ -456,7 +459,8 @@ int enqueue(BatchArgs a, const int blocks[SFT_KERNEL_COUNT], const size_t lds[SF
         a.bps = bps ? bps[k] : 0;
         LaunchFn fn = launcher(k);
         auto launch = [&]() -> hipError_t {
-            if (k != SFT_KERNEL_DFT_MX || !mxs || mxs->j1 <= 0 || prefix) return fn(a, blocks[k], lds[k], st);
+            if (k != SFT_KERNEL_DFT_MX || !mxs || mxs->j1 <= 0 || prefix || blocks[k] < mxs->min_blocks)
+                return fn(a, blocks[k], lds[k], st);
             // moduli [0, j1) with the smaller LDS allocation, then [j1, K)
             const int per = mxs->K * mxs->qb;
             const int count = blocks[k] / per;

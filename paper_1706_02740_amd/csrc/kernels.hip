@@ -13,8 +13,8 @@
 //               by ghat (Algorithm 1: inner sparse FFT, band test, division; Appendix B)
 //   k_merge     global s-term over the bands (Algorithm 1, last step)
 //
-// Workgroups have 256 threads, except k_dft and k_dft_cols_mx (512) and the
-// LDS-key form of k_select (1024).  A launch covers one transform
+// Workgroups have 256 threads, except k_dft and k_dft_cols_mx (512), the
+// LDS-key form of k_select and k_identify in launches of few bands (1024).  A launch covers one transform
 // (BatchArgs::io_many == nullptr) or a batch, where a per-signal block prefix
 // (or, for a batch of one plan, a division) maps blockIdx.x to (signal, local
 // block).  A k_dft launch may cover a range of the moduli only.
@@ -183,11 +183,12 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
 // returns the total.  Each thread scans a contiguous chunk; the chunk sums are
 // scanned by wave shuffles and one exchange of the wave totals.
 // scratch: int32[kThreads / 64].
+template <int NT = kThreads>
 __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    const int chunk = (n + kThreads - 1) / kThreads;
+    const int chunk = (n + NT - 1) / NT;
     const int beg = min(n, tid * chunk);
     const int end = min(n, beg + chunk);
     int sum = 0;
@@ -197,7 +198,7 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
     __syncthreads();
     int base = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         const int v = scratch[w];
         base += w < wid ? v : 0;
         total += v;
@@ -1660,7 +1661,7 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
 }
 
 // ---------------------------------------------------------- k_identify ----
-// One workgroup per band b.  Candidates: in CRT tuple t and residue class a,
+// One workgroup of NT threads per band b.  Candidates: in CRT tuple t and residue class a,
 // one of the `depth` heaviest heavy class-a bins of every modulus of the tuple
 // (the class lists written with the heavy bins);
 // w = a (mod s1), w = h_g (mod p_g) by the CRT in int64, mapped into B.
@@ -1725,8 +1726,8 @@ __device__ bool phase_frequency(float2 e, float2 e2, int h, int P, int64_t N, in
 // bitmaps exceed the LDS, or batches that contain one); otherwise it tests the
 // heavy-bin bitmaps.  Both decide the same way.  PHASE: the launch may hold
 // plans with phase identification (taken per transform).
-template <bool KEYVOTE, bool PHASE>
-__global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
+template <bool KEYVOTE, bool PHASE, int NT>
+__global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
     const CONSTANT SigDesc* d = desc_of(a, at.sig);
@@ -1749,7 +1750,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     float2* az = reinterpret_cast<float2*>(smem + (size_t)acap * 8);
     int32_t* flag = reinterpret_cast<int32_t*>(smem + (size_t)acap * 16);
     int32_t* scratch = flag + acap;
-    int32_t* pre = scratch + kThreads;
+    int32_t* pre = scratch + NT;
     uint8_t* ccount = reinterpret_cast<uint8_t*>(pre + ((nslots + 2) & ~1));   // [K * s1]
     // heavy-bin bitmaps of the band's K blocks (when they fit the LDS): bit h of
     // block jj at word woff[jj] + h / 32; otherwise the vote compares keys
@@ -1768,9 +1769,9 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     const size_t cl_stride = (size_t)s1 * depth;   // one (modulus, band) block of class lists
 
     // 0. class-list lengths and heavy-bin bitmaps of this band's K blocks, into LDS
-    for (int i = tid; i < woff[kMaxK]; i += kThreads) bm[i] = 0;
+    for (int i = tid; i < woff[kMaxK]; i += NT) bm[i] = 0;
     if (!use_bm)
-        for (int jj = tid; jj < K; jj += kThreads) sh_thr[jj] = glb(io.thr)[jj * Q + b];
+        for (int jj = tid; jj < K; jj += NT) sh_thr[jj] = glb(io.thr)[jj * Q + b];
     __syncthreads();   // bitmaps cleared
     {
         // class-list lengths (lists are -1 padded) and the heavy bins of block
@@ -1779,12 +1780,12 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         constexpr int U = 4;
         const int nh = use_bm ? K * T : 0;
         const int ncl = phase ? 0 : K * s1;   // class lists: residue identification only
-        for (int i0 = tid; i0 < ncl || i0 < nh; i0 += U * kThreads) {
+        for (int i0 = tid; i0 < ncl || i0 < nh; i0 += U * NT) {
             int32_t hv[U];
             int32_t lv[U][kMaxDepth];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * kThreads;
+                const int i = i0 + u * NT;
                 hv[u] = -1;
                 if (i < nh) {
                     const int jj = i / T;
@@ -1803,7 +1804,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * kThreads;
+                const int i = i0 + u * NT;
                 if (hv[u] >= 0) {
                     const int jj = i / T;
                     atomicOr(&bm[woff[jj] + (hv[u] >> 5)], 1u << (hv[u] & 31));
@@ -1821,7 +1822,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
 
     // 1. combinations per (tuple, class) slot: product of the class-list lengths
     // (phase identification: one candidate per heavy bin, K T of them)
-    for (int slot = tid; slot < nslots && !phase; slot += kThreads) {
+    for (int slot = tid; slot < nslots && !phase; slot += NT) {
         const int t = slot >> lg;
         const int ac = slot & (s1 - 1);
         int cnt = 1;
@@ -1830,7 +1831,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     }
     if (tid == 0) sh_cnt = 0;
     __syncthreads();
-    const int total = phase ? K * T : block_exclusive_scan(pre, nslots, scratch);
+    const int total = phase ? K * T : block_exclusive_scan<NT>(pre, nslots, scratch);
     if (tid == 0) pre[nslots] = total;
     __syncthreads();
 
@@ -1869,8 +1870,8 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     constexpr bool prefetch = !PHASE;
     Combo cur, nxt;
     if (prefetch && tid < total) prep(tid, cur);
-    for (int c = tid; c < total; c += kThreads) {
-        if (prefetch && c + kThreads < total) prep(c + kThreads, nxt);
+    for (int c = tid; c < total; c += NT) {
+        if (prefetch && c + NT < total) prep(c + NT, nxt);
         {   // candidate c; a dropped candidate jumps to the end of the iteration
             int64_t w;
             int t = 0, jp = 0;   // CRT tuple (residue identification); producing modulus (phase)
@@ -1998,7 +1999,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     __syncthreads();
     const int nacc = min(sh_cnt, acap);
     // 3. sort accepted by key descending (|z|^2 desc, w asc)
-    if (nacc <= 2 * kThreads) {
+    if (nacc <= 2 * NT) {
         // by rank: an entry's position is the number of entries ahead of it
         // (a larger key, or an equal key at a lower index)
         uint64_t kk[2];
@@ -2006,7 +2007,7 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         int rk[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int i = tid + u * kThreads;
+            const int i = tid + u * NT;
             rk[u] = -1;
             if (i < nacc) {
                 const uint64_t k = akey[i];
@@ -2032,14 +2033,14 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
     } else {   // bitonic sort of the entries padded with zero keys to a power of two
         int np2 = 1;
         while (np2 < nacc) np2 <<= 1;
-        for (int i = nacc + tid; i < np2; i += kThreads) {
+        for (int i = nacc + tid; i < np2; i += NT) {
             akey[i] = 0;
             az[i] = make_float2(0.f, 0.f);
         }
         __syncthreads();
         for (int kk = 2; kk <= np2; kk <<= 1) {
             for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int i = tid; i < np2; i += kThreads) {
+                for (int i = tid; i < np2; i += NT) {
                     const int ixj = i ^ jj;
                     if (ixj > i) {
                         const bool desc = (i & kk) == 0;
@@ -2058,9 +2059,9 @@ __global__ void __launch_bounds__(kThreads) k_identify(BatchArgs a) {
         }
     }
     // 4. distinct entries, the first s of them (R_temp), then the band test
-    for (int i = tid; i < nacc; i += kThreads) flag[i] = (i == 0 || akey[i] != akey[i - 1]) ? 1 : 0;
+    for (int i = tid; i < nacc; i += NT) flag[i] = (i == 0 || akey[i] != akey[i - 1]) ? 1 : 0;
     __syncthreads();
-    block_exclusive_scan(flag, nacc, scratch);   // for a distinct entry: its rank among distinct ones
+    block_exclusive_scan<NT>(flag, nacc, scratch);   // for a distinct entry: its rank among distinct ones
     const int64_t q = d->q_first + 2 * (int64_t)b * d->L;
     const int s = d->s;
     GLOBAL int64_t* __restrict__ Rw = glb(io.Rw) + (size_t)b * s;
@@ -2241,10 +2242,14 @@ size_t select_lds_bytes(const SigDesc& d, bool lds_keys) {
 // Dynamic LDS above 64 KiB: raise each kernel's limit where the runtime asks
 // for an opt-in.  A rejected request is not an error here: the launch itself
 // reports a size the device cannot hold.
+static int g_max_lds = 0;   // the smallest per-workgroup LDS limit of the configured devices
+
 hipError_t configure_kernels(int max_lds) {
+    if (g_max_lds == 0 || max_lds < g_max_lds) g_max_lds = max_lds;
     const void* ks[] = {(const void*)k_dft<8, false>, (const void*)k_dft<16, false>, (const void*)k_dft<0, true>,
-                         (const void*)k_identify<false, false>, (const void*)k_identify<true, false>,
-                         (const void*)k_identify<false, true>, (const void*)k_identify<true, true>,
+                         (const void*)k_identify<false, false, kThreads>, (const void*)k_identify<true, false, kThreads>,
+                         (const void*)k_identify<false, true, kThreads>, (const void*)k_identify<true, true, kThreads>,
+                         (const void*)k_identify<false, false, kIdentifyWide>,
                          (const void*)k_merge, (const void*)k_dft_rows,
                          (const void*)k_dft_cols, (const void*)k_dft_cols_mx, (const void*)k_select<kThreads, false>,
                          (const void*)k_select<kSelLdsThreads, true>};
@@ -2315,12 +2320,23 @@ hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream
     // lds carries the byte count in its low 32 bits; bit 32 selects the key
     // vote, bit 33 the kernel that also handles phase identification
     const size_t bytes = lds & 0xffffffffu;
+    const int kind = (int)((lds >> 32) & 3);
     const dim3 g(blocks), t(kThreads);
-    switch ((int)((lds >> 32) & 3)) {
-        case 0: hipLaunchKernelGGL((k_identify<false, false>), g, t, bytes, st, a); break;
-        case 1: hipLaunchKernelGGL((k_identify<true, false>), g, t, bytes, st, a); break;
-        case 2: hipLaunchKernelGGL((k_identify<false, true>), g, t, bytes, st, a); break;
-        default: hipLaunchKernelGGL((k_identify<true, true>), g, t, bytes, st, a); break;
+    // a launch of few bands (a single transform or a small batch) leaves most
+    // CUs idle: give each band a workgroup of kIdentifyWide threads (its
+    // scan partials take (kIdentifyWide - kThreads) ints more).  Bitmap vote
+    // and residue identification only: the other variants need more than the
+    // 128 VGPRs such a workgroup allows.
+    const size_t wbytes = bytes + (size_t)(kIdentifyWide - kThreads) * 4;
+    if (kind == 0 && blocks <= kIdentifyWideMaxBlocks && wbytes + 256 <= (size_t)g_max_lds) {
+        hipLaunchKernelGGL((k_identify<false, false, kIdentifyWide>), g, dim3(kIdentifyWide), wbytes, st, a);
+        return hipGetLastError();
+    }
+    switch (kind) {
+        case 0: hipLaunchKernelGGL((k_identify<false, false, kThreads>), g, t, bytes, st, a); break;
+        case 1: hipLaunchKernelGGL((k_identify<true, false, kThreads>), g, t, bytes, st, a); break;
+        case 2: hipLaunchKernelGGL((k_identify<false, true, kThreads>), g, t, bytes, st, a); break;
+        default: hipLaunchKernelGGL((k_identify<true, true, kThreads>), g, t, bytes, st, a); break;
     }
     return hipGetLastError();
 }

@@ -11,6 +11,8 @@ namespace sft {
 constexpr int kMaxK = SFT_MAX_MODULI;
 constexpr int kMaxG = 7;
 constexpr int kThreads = 256;          // workgroup size of every kernel but k_dft (4 wave64)
+constexpr int kIdentifyWide = 1024;    // k_identify workgroup size for launches of at most
+constexpr int kIdentifyWideMaxBlocks = 64;   // this many bands (a few transforms)
 constexpr int kDftThreads = 512;       // k_dft workgroup size (8 wave64)
 constexpr int kBandChunk = 16;         // bands accumulated per pass of the generic gather kernel (table padding)
 constexpr int kFastTaps = 16;          // window widths with a compile-time gather kernel are at most this
@@ -114,9 +116,11 @@ struct BatchArgs {
 
 // The matrix-core short DFTs of a plan in two launches: moduli [0, j1) with
 // lds_lo bytes per workgroup, then [j1, K) (j1 = 0: one launch).  qb: blocks
-// per modulus of one transform, Q (1 + phase).
+// per modulus of one transform, Q (1 + phase).  Launches of fewer than
+// min_blocks blocks stay whole: with a few blocks per CU, occupancy does not
+// matter and the second launch would only add its latency.
 struct MxSplit {
-    int j1 = 0, K = 0, qb = 0;
+    int j1 = 0, K = 0, qb = 0, min_blocks = 0;
     size_t lds_lo = 0;
 };
 

@@ -313,9 +313,9 @@ def test_split_dft_path_equals_in_lds_path(gpu, N, s, snr, kw):
 def test_split_matrix_core_path_equals_in_lds_matrix_core_path(gpu, N, s, snr, kw):
     """The split path with matrix-core columns performs the p-point step with
     the same operands in the same order as the in-LDS matrix-core kernel:
-    bins, heavy sets and outputs are bitwise equal.  At N = 2^22, s = 64 the
-    in-LDS kernel runs as two launches (the smaller moduli with a smaller LDS
-    allocation), for both identifications."""
+    bins, heavy sets and outputs are bitwise equal, also at N = 2^22, s = 64,
+    a plan that splits its in-LDS launches of many transforms by modulus
+    (a single transform runs as one launch)."""
     say("split mx vs lds mx", N, s, kw)
     sg = siggen.sparse_signal(N, s, seed=21, snr_db=snr)
     f = dev(sg.f32)
@@ -393,8 +393,10 @@ def test_unfilled_slots_are_zero(gpu):
 def test_headline_launch_as_benchmarked(gpu):
     """The headline in the launch configuration the benchmark times: 256
     transforms per execute_many over 32 resident inputs.  Every output equals
-    the plain call on its input bit for bit; two inputs are also checked
-    against the oracle."""
+    the plain call on its input bit for bit (the batch runs the short DFTs as
+    the two launches of the moduli split and the identification with 256
+    threads per band; a plain call runs one short-DFT launch and 1024 threads
+    per band); two inputs are also checked against the oracle."""
     N, s, B, distinct = 2 ** 22, 64, 256, 32
     plan = gpu.Plan(N, s)
     sigs = [siggen.workload("plain_n2e22_s64_20db", seed) for seed in range(distinct)]
@@ -446,7 +448,10 @@ def test_matrix_core_moduli_split_rule(gpu):
     its largest block leaves room for only two workgroups per CU and the
     smaller moduli's blocks fit three: N = 2^22, s = 64 (blocks of 37..61
     columns of 128 bins) splits after the moduli up to 47; N = 2^21, s = 32
-    (64 bins per row) runs as one launch; split path plans report 0."""
+    (64 bins per row) runs as one launch; split path plans report 0.  The
+    split launches themselves are checked against the whole launch of a
+    single transform in test_headline_launch_as_benchmarked and
+    test_phase_headline_n2e22_s64."""
     head = gpu.Plan(2 ** 22, 64)
     assert head.info["dft_path"] == 3
     primes = head.info["primes"]
