@@ -265,7 +265,11 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         for (int st = 0; st < kMxSteps; ++st)
             for (int m = 0; m < kMxTiles; ++m)
                 for (int l = 0; l < 64; ++l) {
-                    const int n = 1 + 4 * st + l / 16, k = 16 * m + l % 16;
+                    // lane l supplies row i = l % 16 of the tile, which the
+                    // in-LDS kernel assigns to k = 16 m + 4 (i % 4) + i / 4 (the
+                    // four rows of an output register are consecutive)
+                    const int i = l % 16;
+                    const int n = 1 + 4 * st + l / 16, k = 16 * m + 4 * (i % 4) + i / 4;
                     float2 v = make_float2(0.f, 0.f);
                     if (n <= hj && k == 0) {
                         v = make_float2(1.f, 0.f);

@@ -1087,8 +1087,9 @@ struct MfmaClassThreads {
 // k0 + kk and p - k0 - kk; slot 2 KBMAX: row 0, group 0 only).
 // MX: step B on the matrix cores (pfa_mfma, up to MT = NTW = 2).  Requires
 // s1 = 64 or 128 and h + 1 <= 32 for every modulus.  Slot (t MT + m) 4 + r
-// holds the key of row k = 16 m + 4 (l / 16) + r of N-tile w + 8 t: X_k in
-// even lanes, X_{p-k} in odd lanes (row 0 in even lanes only).  LDS: the block
+// holds the key of row k = 16 m + 4 r + l / 16 of N-tile w + 8 t: X_k in
+// even lanes, X_{p-k} in odd lanes (row 0 in even lanes only); the rows of a
+// register are consecutive, so registers whose rows all exceed h are skipped.  LDS: the block
 // and the s1 twiddles only (the A operands come from the plan's table in
 // global memory); the selection's scratch reuses the block's space, so a
 // launch over the smaller moduli (BatchArgs::jn) needs less LDS per
@@ -1197,8 +1198,9 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
                 if (m >= mt) break;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    if (16 * m + 4 * r > h) break;   // rows 16 m + 4 r .. + 3: all padding (uniform)
                     const int q = (t * MT + m) * 4 + r;
-                    const int k = 16 * m + 4 * lk + r;
+                    const int k = 16 * m + 4 * r + lk;
                     const float cv = Cm[t][m][r];
                     const float dp = lane_pair(Dm[t][m][r]);
                     const float xk = (x0v + cv + sgn * dp) * scale;
@@ -1257,7 +1259,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     auto pos_of = [&](int q, int th) -> int {
         if constexpr (MT > 0) {
             const int t = q / (MT * 4);
-            const int k = 16 * ((q >> 2) % MT) + 4 * ((th >> 4) & 3) + (q & 3);
+            const int k = 16 * ((q >> 2) % MT) + 4 * (q & 3) + ((th >> 4) & 3);
             const int c = (16 * ((th >> 6) + 8 * t) + (th & 15)) >> 1;
             return (((th & 1) ? p - k : k) << lg) + c;
         } else {
@@ -1275,10 +1277,23 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         asm volatile("" : "+v"(th));
         return 0xffffffffu - pfa_bin(pos_of(q, th), lg, s1, (uint32_t)P, cA, cB);
     };
+    // slots that hold a key in some lane (MX: the register's rows are not all
+    // padding), wave-uniform, so that the passes branch over the others
+    uint32_t live = 0;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        if constexpr (MT > 0) {
+            const int t = q / (MT * 4), m = (q >> 2) % MT, r = q & 3;
+            if (t < (s1 >> 6) && 16 * m + 4 * r <= h) live |= 1u << q;
+        } else {
+            live |= 1u << q;
+        }
+    }
+    live = __builtin_amdgcn_readfirstlane(live);
     auto each = [&](auto f) {
 #pragma unroll
         for (int q = 0; q < NK; ++q)
-            if ((valid >> q) & 1) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q, tid); });
+            if (((live >> q) & 1) && ((valid >> q) & 1)) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q, tid); });
     };
     const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
