@@ -1277,23 +1277,28 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         asm volatile("" : "+v"(th));
         return 0xffffffffu - pfa_bin(pos_of(q, th), lg, s1, (uint32_t)P, cA, cB);
     };
-    // slots that hold a key in some lane (MX: the register's rows are not all
-    // padding), wave-uniform, so that the passes branch over the others
-    uint32_t live = 0;
+    // MX: the slots that hold a key in some lane (the register's rows are not
+    // all padding), wave-uniform, so that the passes branch over the others
+    // (NK <= 32 there; the VALU form has up to 33 slots and no padding slots)
+    uint32_t live = 0xffffffffu;
+    if constexpr (MT > 0) {
+        static_assert(NK <= 32, "one bit per slot");
+        live = 0;
 #pragma unroll
-    for (int q = 0; q < NK; ++q) {
-        if constexpr (MT > 0) {
+        for (int q = 0; q < NK; ++q) {
             const int t = q / (MT * 4), m = (q >> 2) % MT, r = q & 3;
             if (t < (s1 >> 6) && 16 * m + 4 * r <= h) live |= 1u << q;
-        } else {
-            live |= 1u << q;
         }
+        live = __builtin_amdgcn_readfirstlane(live);
     }
-    live = __builtin_amdgcn_readfirstlane(live);
     auto each = [&](auto f) {
 #pragma unroll
-        for (int q = 0; q < NK; ++q)
-            if (((live >> q) & 1) && ((valid >> q) & 1)) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q, tid); });
+        for (int q = 0; q < NK; ++q) {
+            if constexpr (MT > 0) {
+                if (!((live >> q) & 1)) continue;
+            }
+            if ((valid >> q) & 1) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q, tid); });
+        }
     };
     const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);

@@ -74,6 +74,8 @@ INTERMEDIATE_CASES = [
     ("split_n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2, "dft_path": 2}, 3),
     ("splitmx_prime_n100003_s20_30db", 100_003, 20, 30.0, {"dft_path": 4}, 1),
     ("auto_splitmx_n2e20_s100_30db", 2 ** 20, 100, 30.0, {}, 7),   # three row tiles (h = 41)
+    # s1 = 256 with up to 13 output pairs per thread: the 33-slot VALU short DFT
+    ("valu33_n2e18_s100_20db", 2 ** 18, 100, 20.0, {"dft_path": 1}, 8),
 ]
 
 
@@ -290,7 +292,8 @@ def test_serving_mix_results_equal_alone(gpu):
 
 
 @pytest.mark.parametrize("N,s,snr,kw", [(2 ** 14, 8, 30.0, {}), (100_003, 20, 20.0, {}),
-                                        (2 ** 16, 100, 10.0, {"preset": 1}), (2 ** 14, 8, None, {"preset": 2})])
+                                        (2 ** 16, 100, 10.0, {"preset": 1}), (2 ** 14, 8, None, {"preset": 2}),
+                                        (2 ** 18, 100, 20.0, {}), (2 ** 22, 128, 20.0, {})])
 def test_split_dft_path_equals_in_lds_path(gpu, N, s, snr, kw):
     """The split short-DFT kernels perform the same arithmetic in the same order
     as the in-LDS kernel: bins, heavy sets and outputs are bitwise equal."""
