@@ -2157,35 +2157,68 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
         ww[e] = glb(io.Rw)[(size_t)lo * s + k];
         src[e] = lo * s + k;
     }
-    int np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    for (int i = n + tid; i < np2; i += kThreads) {
-        mm[i] = -1.0;
-        ww[i] = 0;
-        src[i] = -1;
-    }
     __syncthreads();
-    for (int kk = 2; kk <= np2; kk <<= 1) {
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < np2; i += kThreads) {
-                const int ixj = i ^ jj;
-                if (ixj > i) {
-                    const bool up = (i & kk) == 0;
-                    const double mi = mm[i], mx = mm[ixj];
-                    const int64_t wi = ww[i], wx = ww[ixj];
-                    const bool sw = up ? merge_before(mx, wx, mi, wi) : merge_before(mi, wi, mx, wx);
-                    if (sw) {
-                        mm[i] = mx;
-                        mm[ixj] = mi;
-                        ww[i] = wx;
-                        ww[ixj] = wi;
-                        const int32_t t = src[i];
-                        src[i] = src[ixj];
-                        src[ixj] = t;
+    if (n <= 2 * kThreads) {
+        // by rank: an entry's position is the number of entries ordered before
+        // it (the frequencies of a transform are distinct, so the ranks are)
+        double mv[2];
+        int64_t wv[2];
+        int32_t sv[2];
+        int rk[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = tid + u * kThreads;
+            rk[u] = -1;
+            if (i < n) {
+                mv[u] = mm[i];
+                wv[u] = ww[i];
+                sv[u] = src[i];
+                int r = 0;
+                for (int j = 0; j < n; ++j) r += merge_before(mm[j], ww[j], mv[u], wv[u]) ? 1 : 0;
+                rk[u] = r;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (rk[u] >= 0) {
+                mm[rk[u]] = mv[u];
+                ww[rk[u]] = wv[u];
+                src[rk[u]] = sv[u];
+            }
+        }
+        __syncthreads();
+    } else {   // bitonic sort of the entries padded to a power of two
+        int np2 = 1;
+        while (np2 < n) np2 <<= 1;
+        for (int i = n + tid; i < np2; i += kThreads) {
+            mm[i] = -1.0;
+            ww[i] = 0;
+            src[i] = -1;
+        }
+        __syncthreads();
+        for (int kk = 2; kk <= np2; kk <<= 1) {
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int i = tid; i < np2; i += kThreads) {
+                    const int ixj = i ^ jj;
+                    if (ixj > i) {
+                        const bool up = (i & kk) == 0;
+                        const double mi = mm[i], mx = mm[ixj];
+                        const int64_t wi = ww[i], wx = ww[ixj];
+                        const bool sw = up ? merge_before(mx, wx, mi, wi) : merge_before(mi, wi, mx, wx);
+                        if (sw) {
+                            mm[i] = mx;
+                            mm[ixj] = mi;
+                            ww[i] = wx;
+                            ww[ixj] = wi;
+                            const int32_t t = src[i];
+                            src[i] = src[ixj];
+                            src[ixj] = t;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     const int nout = min(n, s);
