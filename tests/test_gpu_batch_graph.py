@@ -63,3 +63,35 @@ def test_graph_replays_equal_eager(gpu):
         gpu.execute_many(plans, sets[(r + 1) % 4])
         torch.cuda.synchronize()
     batch.close()
+
+
+def test_graph_replay_of_split_launches(gpu):
+    """A one-plan batch large enough for the moduli split of the matrix-core
+    short DFTs (32 transforms at N = 2^22, s = 64: two launches), captured once
+    and replayed on two input sets: every replay equals the plain calls (one
+    short-DFT launch each) bit for bit."""
+    N, s, B = 2 ** 22, 64, 32
+    plan = gpu.Plan(N, s)
+    assert plan.info["dft_split"] > 0
+    sigs = [dev(siggen.workload("plain_n2e22_s64_20db", i).f32) for i in range(4)]
+    bufs = [torch.empty_like(sigs[0]) for _ in range(B)]
+    batch = gpu.Batch([plan] * B, bufs)
+    st = torch.cuda.Stream()   # default priority
+    for r in range(2):
+        say("split graph replay", r)
+        for i, b in enumerate(bufs):
+            b.copy_(sigs[(i + r) % 4])
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            outs, counts = batch.graph_launch(st)
+        st.synchronize()
+        plain = []
+        for f in sigs:
+            w, c, n = plan.execute(f)
+            torch.cuda.synchronize()
+            plain.append((w.clone(), c.clone(), int(n.item())))
+        for i in range(B):
+            w, c, n = plain[(i + r) % 4]
+            assert int(counts[i].item()) == n, i
+            assert torch.equal(outs[i][0], w) and torch.equal(outs[i][1], c), i
+    batch.close()
