@@ -1680,6 +1680,16 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
     emit_heavy<NT>(kf, P, d->T, s1, d->depth, thr, hk, hist, part, cl, Hout, thr_out, CLout);
 }
 
+// a mod d for a 32-bit a, from magic = floor((2^64 - 1) / d) + 1 (Lemire,
+// Kaser and Kurz 2019): the bits [64, 96) of (magic a mod 2^64) d, formed
+// from two 32 x 32-bit products.
+__device__ __forceinline__ uint32_t fastmod_u32(uint32_t a, uint64_t magic, uint32_t d) {
+    const uint64_t low = magic * (uint64_t)a;
+    const uint64_t lo_d = (uint64_t)(uint32_t)low * d;
+    const uint64_t hi_d = (uint64_t)(uint32_t)(low >> 32) * d;
+    return (uint32_t)((hi_d + (lo_d >> 32)) >> 32);
+}
+
 // ---------------------------------------------------------- k_identify ----
 // One workgroup of NT threads per band b.  Candidates: in CRT tuple t and residue class a,
 // one of the `depth` heaviest heavy class-a bins of every modulus of the tuple
@@ -1879,8 +1889,11 @@ __global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
             if (g < G) {
                 const int jj = d->tup_j[cb.t][g];
                 const int cg = ccount[(jj << lg) + cb.ac];
-                const int ch = r % cg;
-                r /= cg;
+                // r < 64 and cg <= kMaxDepth: (r + 1/2) / cg lies at least 1/16
+                // from an integer, far beyond the reciprocal's rounding
+                const int qd = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)cg));
+                const int ch = r - qd * cg;
+                r = qd;
                 cb.hg[g] = CLall[(size_t)(jj * Q + b) * cl_stride + (size_t)cb.ac * depth + ch];
             }
         }
@@ -1913,8 +1926,9 @@ __global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
             for (int g = 0; g < kMaxG; ++g) {
                 if (g < G) {
                     const uint32_t pm = (uint32_t)d->tup_mod[t][g + 1];
-                    const uint32_t res = (uint32_t)cur.hg[g] % pm;
-                    x += (int64_t)((res * (uint32_t)d->tup_inv[t][g + 1]) % pm) * d->tup_Mi[t][g + 1];
+                    const uint64_t mg = d->magic_p[d->tup_j[t][g]];   // pm = p of that modulus
+                    const uint32_t res = fastmod_u32((uint32_t)cur.hg[g], mg, pm);
+                    x += (int64_t)fastmod_u32(res * (uint32_t)d->tup_inv[t][g + 1], mg, pm) * d->tup_Mi[t][g + 1];
                 }
             }
             const int64_t Mt = d->tup_M[t];
@@ -1938,7 +1952,7 @@ __global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
                 for (int jj = 0; jj < kMaxK; ++jj) {
                     if (jj < K) {
                         const int Pj = d->P[jj];
-                        const int k2 = hh[jj] % d->p[jj];
+                        const int k2 = (int)fastmod_u32((uint32_t)hh[jj], d->magic_p[jj], (uint32_t)d->p[jj]);
                         const float2 ev = ld2(Eall + (size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) +
                                               (hh[jj] & (s1 - 1)));
                         er[jj] = ev.x;
@@ -1949,9 +1963,10 @@ __global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
 #pragma unroll
             for (int jj = 0; jj < kMaxK; ++jj) {
                 if (jj < K) {
-                    if (small_n) {   // w fits 32 bits
-                        const int r32 = (int)w % d->P[jj];
-                        hh[jj] = r32 < 0 ? r32 + d->P[jj] : r32;
+                    if (small_n) {   // w - lo fits 32 bits: w mod P = ((w - lo) mod P + lo mod P) mod P
+                        const int Pj = d->P[jj];
+                        const int r = (int)fastmod_u32((uint32_t)(w - lo), d->magic_P[jj], (uint32_t)Pj) + d->lo_mod_P[jj];
+                        hh[jj] = r >= Pj ? r - Pj : r;
                     } else {
                         hh[jj] = (int)pos_mod(w, d->P[jj]);
                     }

@@ -193,6 +193,9 @@ void fill_desc(const sft_plan_info& in, SigDesc* d) {
         twoff += in.primes[j];
         d->trig_off[j] = trigoff;
         trigoff += ((in.primes[j] - 1) / 2) * ((in.primes[j] - 1) / 2);
+        d->magic_p[j] = UINT64_MAX / (uint64_t)in.primes[j] + 1;
+        d->magic_P[j] = UINT64_MAX / (uint64_t)in.P[j] + 1;
+        d->lo_mod_P[j] = (int32_t)(((d->lo % in.P[j]) + in.P[j]) % in.P[j]);
     }
     d->Moff[in.K] = off;
     for (int t = 0; t < 2; ++t) {

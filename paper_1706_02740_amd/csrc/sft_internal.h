@@ -65,6 +65,12 @@ struct SigDesc {
     int64_t tup_Mi[2][kMaxG + 1];
     int32_t tup_inv[2][kMaxG + 1];
     int32_t tup_mod[2][kMaxG + 1];
+    // exact remainders by multiplication for the identification's divisors
+    // (Lemire, Kaser and Kurz, "Faster remainder by direct computation", 2019):
+    // magic = floor((2^64 - 1) / d) + 1, valid for every 32-bit dividend
+    uint64_t magic_p[kMaxK];   // d = p_j
+    uint64_t magic_P[kMaxK];   // d = P_j
+    int32_t lo_mod_P[kMaxK];   // lo mod P_j, in [0, P_j)
     // device tables owned by the plan
     const float2* bandtab;   // [Q][taps]: exp(-2 pi i ((q_b (i - kappa)) mod N) / N)
     const float2* tw_s1;     // [s1/2]: exp(-2 pi i k / s1)
@@ -73,7 +79,7 @@ struct SigDesc {
     const float2* trig;      // concatenated [h_j^2]: (cos, sin)(2 pi (n k mod p_j) / p_j), n, k in [1, h_j]
     int32_t trig_off[kMaxK];
     // [K][kMxSteps][kMxTiles][64]: the matrix-core step's A operands in lane order;
-    // lane l of step st, tile m: n = 1 + 4 st + l / 16, k = 16 m + l % 16 ->
+    // lane l of step st, tile m, i = l % 16: n = 1 + 4 st + l / 16, k = 16 m + 4 (i % 4) + i / 4 ->
     // (cos, sin)(2 pi (n k mod p) / p) for n, k in [1, h]; (1, 0) for k = 0 < n <= h; else 0
     const float2* mxa;
     // [K][kMxcSteps][kMxcTiles][64]: the same operands for the split path's
