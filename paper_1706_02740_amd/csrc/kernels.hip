@@ -1992,6 +1992,17 @@ __global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
                 }
             }
             if (2 * votes > need) {
+                if constexpr (use_bm && !PHASE) {
+                    // the bitmap-vote residue kernel keeps only w here; the bins and
+                    // the median follow for all accepted candidates at once after the
+                    // loop, so that no wave waits on bin loads in it (the kernel that
+                    // may also run phase identification reads them here: deferring
+                    // there too multiplied its registers)
+                    const int pos = atomicAdd(&sh_cnt, 1);
+                    if (pos < acap) akey[pos] = (uint64_t)(0xffffffffu - (uint32_t)(w - lo));
+                    else atomicOr(io.status, kStatusAcceptOverflow);
+                    goto next_candidate;
+                }
                 if constexpr (use_bm) read_bins(er, ei);
                 if (PHASE && phase) {
                     // one entry per frequency: an earlier modulus whose heavy bin at w
@@ -2033,6 +2044,43 @@ __global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
     }
     __syncthreads();
     const int nacc = min(sh_cnt, acap);
+    if constexpr (use_bm && !PHASE) {
+        // the accepted candidates' bins in every modulus (all loads of a thread
+        // issued together) and their componentwise median
+        for (int i = tid; i < nacc; i += NT) {
+            const int64_t w = lo + (int64_t)(0xffffffffu - (uint32_t)(akey[i] & 0xffffffffu));
+            float er[kMaxK], ei[kMaxK];
+            float2 ev[kMaxK];
+#pragma unroll
+            for (int jj = 0; jj < kMaxK; ++jj) {
+                if (jj < K) {
+                    const int Pj = d->P[jj];
+                    int h;
+                    if (small_n) {
+                        const int r = (int)fastmod_u32((uint32_t)(w - lo), d->magic_P[jj], (uint32_t)Pj) + d->lo_mod_P[jj];
+                        h = r >= Pj ? r - Pj : r;
+                    } else {
+                        h = (int)pos_mod(w, Pj);
+                    }
+                    const int k2 = (int)fastmod_u32((uint32_t)h, d->magic_p[jj], (uint32_t)d->p[jj]);
+                    ev[jj] = ld2(Eall + (size_t)Q * d->Moff[jj] + (size_t)b * Pj + ((size_t)k2 << lg) + (h & (s1 - 1)));
+                }
+            }
+#pragma unroll
+            for (int jj = 0; jj < kMaxK; ++jj) {
+                if (jj < K) {
+                    er[jj] = ev[jj].x;
+                    ei[jj] = ev[jj].y;
+                }
+            }
+            const float zr = median_of(er, K);
+            const float zi = median_of(ei, K);
+            const float m2 = fmaf(zr, zr, zi * zi);
+            akey[i] |= (uint64_t)__float_as_uint(m2) << 32;
+            az[i] = make_float2(zr, zi);
+        }
+        __syncthreads();
+    }
     // 3. sort accepted by key descending (|z|^2 desc, w asc)
     if (nacc <= 2 * NT) {
         // by rank: an entry's position is the number of entries ahead of it
