@@ -1757,7 +1757,7 @@ __device__ bool phase_frequency(float2 e, float2 e2, int h, int P, int64_t N, in
 // heavy-bin bitmaps.  Both decide the same way.  PHASE: the launch may hold
 // plans with phase identification (taken per transform).
 template <bool KEYVOTE, bool PHASE, int NT>
-__global__ void __launch_bounds__(NT) k_identify(BatchArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOTE || PHASE) ? 1 : 6))) k_identify(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
     const CONSTANT SigDesc* d = desc_of(a, at.sig);
