@@ -316,16 +316,30 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
         const int64_t jc = jp + sh;   // window centre
         GLOBAL float2* __restrict__ S = glb(sh ? io.S2 : io.S) + soff;
         float2 x[TAPS];
-        if ((jc - kappa >= 0) && (jc + kappa < N)) {   // the window in 16-byte pieces (8-byte aligned)
-            typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
-            const GLOBAL f4u* w4 = (const GLOBAL f4u*)(f + (jc - kappa));
+        if ((jc - kappa >= 0) && (jc + kappa + 1 < N)) {
+            // the window in 16-byte-aligned pieces from the even index at or
+            // below its start: (TAPS + 1) / 2 loads, none crossing a 16-byte
+            // boundary, all within the window's lines (the extra value shares a
+            // piece with the first or the last tap); then a shift by the start's parity
+            const int64_t st0 = jc - kappa;
+            const GLOBAL pod_f4* w4 = (const GLOBAL pod_f4*)(f + (st0 & ~(int64_t)1));
+            static_assert(TAPS & 1, "2 kappa + 1 taps");
+            float2 c[TAPS + 1];
 #pragma unroll
-            for (int i = 0; i + 1 < TAPS; i += 2) {
-                const f4u v = w4[i >> 1];   // plain loads: a thread's next load reads the same line
-                x[i] = make_float2(v.x, v.y);
-                x[i + 1] = make_float2(v.z, v.w);
+            for (int i = 0; i < TAPS + 1; i += 2) {
+                const pod_f4 v = w4[i >> 1];   // plain loads: a thread's next load reads the same line
+                c[i] = make_float2(v.x, v.y);
+                c[i + 1] = make_float2(v.z, v.w);
             }
-            if (TAPS & 1) x[TAPS - 1] = ld2(f + (jc - kappa + TAPS - 1));
+            // select by bit masks (a conditional select of c[i] and c[i + 1]
+            // may become an indexed access that puts c in scratch memory)
+            const uint32_t m = 0u - (uint32_t)(st0 & 1);
+#pragma unroll
+            for (int i = 0; i < TAPS; ++i) {   // in place: c[i + 1] is read before it is replaced
+                c[i].x = __uint_as_float((__float_as_uint(c[i].x) & ~m) | (__float_as_uint(c[i + 1].x) & m));
+                c[i].y = __uint_as_float((__float_as_uint(c[i].y) & ~m) | (__float_as_uint(c[i + 1].y) & m));
+                x[i] = c[i];
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < TAPS; ++i) {
