@@ -1459,13 +1459,16 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
     const int p = d->p[j];
     const int P = d->P[j];
     const int h = (p - 1) >> 1;
-    int pmax = 0;
-    for (int jj = 0; jj < d->K; ++jj) pmax = max(pmax, d->p[jj]);
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
-    float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]
-    float2* At = tile + (size_t)pmax * C;           // [kMxcSteps][kMxcTiles][64]
+    float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]: the only LDS
     GLOBAL float2* __restrict__ E = glb(shifted ? io.E2 : io.E) + base;
+    // the A operands [kMxcSteps][kMxcTiles][64] come from the plan's table
+    // (L2-resident), one K-step ahead, as in k_dft
     const GLOBAL float2* __restrict__ A = glb(d->mxc) + (size_t)j * kMxcSteps * kMxcTiles * 64;
+    constexpr int MT = kMxcTiles;
+    float2 a0[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) a0[m] = ld2(A + m * 64 + (tid & 63));
     constexpr int U = 8;   // loads of a thread in flight before its LDS writes
     for (int i0 = tid; i0 < p * C; i0 += U * NT) {
         float2 v[U];
@@ -1480,16 +1483,11 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
             if (i < p * C) tile[i] = v[u];
         }
     }
-    for (int i = tid; i < kMxcSteps * kMxcTiles * 64; i += NT) At[i] = ld2(A + i);
     __syncthreads();
-    constexpr int MT = kMxcTiles;
     mf4 Cm[1][MT], Dm[1][MT];
     const float* bf = reinterpret_cast<const float*>(tile);
     const int mt = (h + 16) >> 4;
-    float2 a0[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) a0[m] = At[m * 64 + (tid & 63)];
-    pfa_mfma<MT, 1, kMxcTiles>(bf, C, p, h, mt, 1, static_cast<const float2*>(At), a0, Cm, Dm);
+    pfa_mfma<MT, 1, kMxcTiles>(bf, C, p, h, mt, 1, A, a0, Cm, Dm);
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int li = lane & 15;
@@ -2348,7 +2346,7 @@ bool cols_mx_covers(const SigDesc& d) {
 size_t cols_mx_lds_bytes(const SigDesc& d) {
     int pmax = 0;
     for (int j = 0; j < d.K; ++j) pmax = std::max(pmax, d.p[j]);
-    return (size_t)pmax * 64 * 8 + (size_t)kMxcSteps * kMxcTiles * 64 * 8 + 64;
+    return (size_t)pmax * 64 * 8 + 64;
 }
 int select_blocks(const SigDesc& d) { return d.K * d.Q; }
 
