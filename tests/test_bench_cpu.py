@@ -1,0 +1,66 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic byte counts of the
+roofline, the scaling of the rocprofv3 traffic counters and its staleness
+check, and the one-GPU guard."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+import paper_1706_02740_amd as sft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_algorithmic_bytes_of_the_headline():
+    """N = 2^22, s = 64: M = 43,648 nodes per band, Q = 16 bands, 13 taps.
+    The gather reads 13 complex64 per node and writes Q samples per node; the
+    short DFTs read and write every sample once."""
+    info = sft.describe(2 ** 22, 64)
+    assert info["M"] == 43_648 and info["Q"] == 16
+    work = bench.kernel_work(info)
+    gather_bytes, gather_flops = work["k_gather"]
+    assert gather_bytes == 43_648 * 13 * 8 + 16 * 43_648 * 8          # 4.54 MB + 5.59 MB
+    assert gather_flops == 16 * 43_648 * 13 * 8
+    dft_bytes, _ = work["k_dft_mx"]
+    assert dft_bytes == 2 * 16 * 43_648 * 8 == work["k_dft"][0]
+
+
+def _traffic_file(path, sha, fetch_kib, write_kib):
+    with open(path, "w") as fh:
+        fh.write("# test\n")
+        fh.write(f"kernels_sha256: {sha}\ncopy_bytes: {2 ** 30}\ntransforms_per_launch: 256\n")
+        fh.write(f"copy fetch_kib: {2 ** 20 / 2}\ncopy write_kib: {2 ** 20}\n")
+        fh.write(f"k_dft_mx fetch_kib: {fetch_kib}\nk_dft_mx write_kib: {write_kib}\n")
+
+
+def test_traffic_counters_are_scaled_by_the_copy_calibration(tmp_path, monkeypatch):
+    """A copy of 1 GiB whose FETCH_SIZE reads half its bytes gives a fetch
+    scale of 2 and a write scale of 1."""
+    sha = hashlib.sha256(open(bench.KERNELS_SRC, "rb").read()).hexdigest()
+    f = tmp_path / "traffic.txt"
+    _traffic_file(f, sha, fetch_kib=1000.0, write_kib=3000.0)
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    tr = bench.measured_traffic("k_dft_mx")
+    assert tr["fetch_scale"] == pytest.approx(2.0) and tr["write_scale"] == pytest.approx(1.0)
+    assert tr["fetch_bytes"] == pytest.approx(1000.0 * 1024 * 2)
+    assert tr["bytes"] == pytest.approx(1000.0 * 1024 * 2 + 3000.0 * 1024)
+    assert tr["transforms_per_launch"] == 256
+
+
+def test_traffic_counters_of_other_kernel_sources_are_ignored(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.txt"
+    _traffic_file(f, "0" * 64, fetch_kib=1000.0, write_kib=3000.0)
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("k_dft_mx") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic("k_dft_mx") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
