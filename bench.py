@@ -37,25 +37,31 @@ WORKLOAD = "plain_n2e22_s64_20db"
 
 
 def kernel_work(info: dict) -> dict:
-    """Algorithmic bytes and flops of one transform, per kernel.
+    """Algorithmic bytes, flops and written-but-not-algorithmic bytes of one
+    transform, per kernel: (bytes, flops, overhead_bytes).
 
+    The algorithmic bytes are what the method must move (Algorithm 1 with the
+    short DFTs of Appendix B): the window values of every node, the filtered
+    samples written once and read once by the short DFTs.
     k_gather : reads the 2 kappa + 1 window values of every node (8 B each) and
                writes Q complex64 samples per node; 8 (2 kappa + 1) flops per
                sample (a real-weighted tap times a band phasor, accumulated).
-    k_dft,   : reads the Q M samples and writes the Q M bins (8 B each); flops
-    k_dft_mx   of the row FFTs (5 P log2 s1 per DFT) and of the even/odd p-point
-               step (8 s1 h^2, h = (p - 1) / 2, per DFT).
+    k_dft,   : read the Q M samples (8 B each).  They also write every bin E,
+    k_dft_mx   Q M x 8 B, which the method needs only at the heavy bins and the
+               accepted candidates' bins: counted as overhead, not as
+               algorithmic bytes.  Flops of the row FFTs (5 P log2 s1 per DFT)
+               and of the even/odd p-point step (8 s1 h^2, h = (p - 1) / 2, per DFT).
     Both sit below the FP32 ridge (about 9.8 flop/B without packed FP32), so
     their roofline is HBM bandwidth.
     """
     Q, M, taps, s1 = info["Q"], info["M"], 2 * info["kappa"] + 1, info["s1"]
     gather_bytes = M * taps * 8 + Q * M * 8
     gather_flops = Q * M * taps * 8
-    dft_bytes = 2 * Q * M * 8
+    dft_bytes = Q * M * 8
     lg = int(math.log2(s1))
     dft_flops = Q * sum(5 * P * lg + 8 * s1 * ((p - 1) // 2) ** 2 for P, p in zip(info["P"], info["primes"]))
-    return {"k_gather": (gather_bytes, gather_flops), "k_dft": (dft_bytes, dft_flops),
-            "k_dft_mx": (dft_bytes, dft_flops)}
+    return {"k_gather": (gather_bytes, gather_flops, 0), "k_dft": (dft_bytes, dft_flops, Q * M * 8),
+            "k_dft_mx": (dft_bytes, dft_flops, Q * M * 8)}
 
 
 def measured_traffic(kernel: str):
@@ -85,6 +91,31 @@ def measured_traffic(kernel: str):
     return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
             "fetch_scale": f_scale, "write_scale": w_scale,
             "transforms_per_launch": int(vals.get("transforms_per_launch", "256"))}
+
+
+def roofline_of(dom: str, work: dict, kern: dict, tpl: dict, info: dict):
+    """The roofline object of kernel `dom`: algorithmic bytes per launch (the
+    per-transform figure of kernel_work times the transforms of a launch)
+    over its mean launch time from the HIP events; the HBM traffic the
+    counters measured (or null when they are stale); the bytes the kernel
+    writes beyond the algorithmic count."""
+    if dom not in work or kern[dom]["avg_ms"] <= 0:
+        return None
+    byts, flops, extra = work[dom]
+    ach = byts * tpl[dom] / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+    tr = measured_traffic(dom)
+    if tr and tr["transforms_per_launch"] != tpl[dom]:   # counters taken at another batch size
+        tr = None
+    return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None,
+            "traffic_detail": tr,
+            "algorithmic_bytes_per_launch": byts * tpl[dom],
+            "overhead_bytes_per_launch": extra * tpl[dom],
+            "overhead": "the bins E written in full (the method reads them only at heavy bins "
+                        "and accepted candidates)" if extra else None,
+            "avg_launch_ms": kern[dom]["avg_ms"], "transforms_per_launch": tpl[dom],
+            # a k_dft_mx launch of a split plan is two dispatches (smaller moduli, then the rest)
+            "dispatches_per_launch": 2 if dom == "k_dft_mx" and info.get("dft_split") else 1}
 
 
 def uneven_batch(sft, siggen, torch, stream, reps: int = 3) -> dict:
@@ -156,13 +187,17 @@ def serving_runs(sft, siggen, torch, distinct: int = 256, arrivals: int = 1024,
         reqs = [serve.Request(rid=i, plan=inputs[i % distinct][0], f=inputs[i % distinct][1], arrival=t,
                               nbytes=serve.footprint_bytes(inputs[i % distinct][0]))
                 for i, t in enumerate(arrival_times)]
-        srv = serve.Server(serve.GpuExecutor(slots=2), budget_bytes=budget, max_batch=256)
+        ex = serve.GpuExecutor(slots=2, reserve_bytes=budget // 2, max_batch=256)
+        srv = serve.Server(ex, budget_bytes=budget, max_batch=256, slot_budget=budget // 2)
         t0 = time.perf_counter()
         serve.run_trace(srv, reqs)
         torch.cuda.synchronize()
         span = time.perf_counter() - t0
+        ex.close()
+        errors = sum(1 for r in srv.completed if r.error)
         lat = np.array([r.latency for r in srv.completed]) * 1e3
         return {"requests": len(srv.completed), "sft_per_s": len(srv.completed) / span, "batches": srv.batches,
+                "overflowed": errors,
                 "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}
 
     trace([0.0] * distinct)   # warm-up: arenas and kernels
@@ -303,6 +338,129 @@ def tuning_sweep(sft, torch, batch: int = 64,
     return {"batch": batch, "shapes": out}
 
 
+# Further configurations, each measured like the headline.  (label, N, s,
+# plan parameters, SNR dB, coefficient magnitudes, batch, distinct inputs).
+# The prime length exercises the wrap-around windows and a non-power-of-two
+# node geometry; the theory preset (Theorem 4: kappa = 22, 45 taps, Q = 40 at
+# N = 2^22) is the ALU-heavy gather; dmsft4 is Section 5's 9-tap window.
+EXTRA_WORKLOADS = [
+    ("prime_n10000019_s128_40db", 10_000_019, 128, {}, 40.0, "loguniform", 128, 8),
+    ("theory_n2e22_s64_20db", 2 ** 22, 64, {"preset": "theory"}, 20.0, "unit", 256, 16),
+    ("dmsft4_n2e22_s64_20db", 2 ** 22, 64, {"preset": "dmsft4"}, 20.0, "unit", 256, 16),
+]
+ORACLE_CHECK_SEED = 0   # the input of each further configuration checked against the oracle
+
+
+def _oracle_job(job):
+    """Worker of the CPU baseline's accuracy jobs: one input of a further
+    configuration (numpy generator, seed ORACLE_CHECK_SEED) through the oracle."""
+    import oracle
+    import siggen
+    label, N, s, kw, snr, mag = job[:6]
+    okw = dict(kw)
+    if isinstance(okw.get("preset"), str):
+        okw["preset"] = {"dmsft6": 0, "dmsft4": 1, "theory": 2}[okw["preset"]]
+    sg = siggen.sparse_signal(N, s, ORACLE_CHECK_SEED, snr, mag)
+    op = oracle.make_plan(N, s, oracle.Params(**okw))
+    t0 = time.perf_counter()
+    w, c = oracle.sft(op, sg.f32)
+    return label, time.perf_counter() - t0, w.tolist(), c.tolist()
+
+
+def oracle_jobs(jobs, workers: int) -> dict:
+    """The oracle on one input of every further configuration, in forked
+    single-threaded processes before the GPU is touched."""
+    import multiprocessing
+    if not jobs:
+        return {}
+    ctx = multiprocessing.get_context("fork")
+    with ctx.Pool(min(len(jobs), workers)) as pool:
+        res = pool.map(_oracle_job, jobs)
+    return {label: {"seconds": dt, "freqs": w, "coefs": c} for label, dt, w, c in res}
+
+
+def compare_with_oracle(wg, cg, ref) -> dict:
+    wo, co = np.array(ref["freqs"], dtype=np.int64), np.array(ref["coefs"])
+    out = {"supports_equal": sorted(wg.tolist()) == sorted(wo.tolist()), "oracle_seconds": ref["seconds"]}
+    if out["supports_equal"]:
+        d = dict(zip(wo.tolist(), co))
+        out["rel_l2"] = math.sqrt(sum(abs(x - d[int(q)]) ** 2 for q, x in zip(wg, cg)) / sum(abs(v) ** 2 for v in co))
+    return out
+
+
+def workload_throughput(sft, siggen, torch, stream, spec, steps: int, oracle_ref=None) -> dict:
+    """A further configuration measured like the headline: `distinct` resident
+    inputs (device generator), `steps` timed batched calls of `batch`
+    transforms with per-kernel HIP events, a pass of plain calls over the
+    same inputs and per-call latency; the batch's status flags; the
+    ORACLE_CHECK_SEED input (numpy generator, as the oracle saw it) against
+    the oracle's output."""
+    label, N, s, kw, snr, mag, B, distinct = spec
+    plan = sft.Plan(N, s, **kw)
+    info = plan.info
+    fs = [siggen.sparse_signal_device(N, s, 9_000_000 + seed, snr, mag)[0] for seed in range(distinct)]
+    inputs = [fs[i % distinct] for i in range(B)]
+    outs = [(torch.empty(s, dtype=torch.int64, device="cuda"), torch.empty(s, dtype=torch.complex64, device="cuda"))
+            for _ in range(B)]
+    counts = torch.empty(B, dtype=torch.int32, device="cuda")
+    sft.execute_many([plan] * B, inputs, outs, counts, stream)
+    torch.cuda.synchronize()
+    sft.profile_reset()
+    sft.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sft.execute_many([plan] * B, inputs, outs, counts, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sft.profile_enable(False)
+    flags = sft.execute_many_status(stream, B)
+    kern, tpl = {}, {}
+    for kid, name in sft.KERNEL_NAMES.items():
+        n, ms = sft.profile_read(kid)
+        if n:
+            kern[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n}
+            tpl[name] = B * steps / n
+    work = kernel_work(info)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    per_kernel = {name: {"GBps": work[name][0] * tpl[name] / (kern[name]["avg_ms"] * 1e-3) / 1e9,
+                         "hbm_frac": work[name][0] * tpl[name] / (kern[name]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "TFLOPs": work[name][1] * tpl[name] / (kern[name]["avg_ms"] * 1e-3) / 1e12}
+                  for name in kern if name in work}
+    pouts = plan.outputs()
+    t0 = time.perf_counter()
+    for f in inputs:
+        plan.execute(f, pouts)
+    torch.cuda.synchronize()
+    plain_rate = B / (time.perf_counter() - t0)
+    lat = []
+    for i in range(min(50, 2 * distinct)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        plan.execute(fs[i % distinct], pouts)
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - a))
+    acc = None
+    if oracle_ref is not None:
+        sg = siggen.sparse_signal(N, s, ORACLE_CHECK_SEED, snr, mag)
+        w, c, n = plan.execute(torch.from_numpy(sg.f32).cuda(), pouts)
+        torch.cuda.synchronize()
+        k = int(n.item())
+        acc = compare_with_oracle(w.cpu().numpy()[:k], c.cpu().numpy()[:k], oracle_ref)
+    rate = B * steps / dt
+    print(f"[bench] {label}: batched {1e3 * dt / steps:.3f} ms per {B} ({rate:.0f} SFT/s), plain {plain_rate:.0f} SFT/s, "
+          f"p50 {np.percentile(lat, 50):.3f} ms; kernels " +
+          ", ".join(f"{k} {v['avg_ms']:.3f}" for k, v in kern.items()), file=sys.stderr, flush=True)
+    return {"N": N, "s": s, "params": kw, "snr_db": snr, "magnitudes": mag, "batch": B, "distinct_inputs": distinct,
+            "plan": {k: info[k] for k in ("Q", "K", "kappa", "s1", "M", "dft_path", "dft_split")},
+            "batched_sft_per_s": rate, "ms_per_step": 1e3 * dt / steps,
+            "plain_sft_per_s": plain_rate, "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "filtered_samples_per_s": rate * info["Q"] * info["M"],
+            "status_flags_nonzero": int(sum(1 for v in flags if v)),
+            "kernels": kern, "kernel_rooflines": per_kernel, "dominant": dom,
+            "roofline": roofline_of(dom, work, kern, tpl, info), "accuracy": acc}
+
+
 def _oracle_worker(seeds):
     """One CPU worker of the baseline: generates its inputs (not timed), then
     times the FP64 oracle on them in this single-threaded process."""
@@ -315,6 +473,24 @@ def _oracle_worker(seeds):
     outs = [oracle.sft(op, sg.f32) for sg in sigs]
     dt = time.perf_counter() - t0
     return list(seeds), dt, [(w.tolist(), c.tolist()) for w, c in outs]
+
+
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, those this process may
+    use, and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
 
 
 def cpu_baseline(distinct: int, workers: int) -> tuple:
@@ -336,7 +512,7 @@ def cpu_baseline(distinct: int, workers: int) -> tuple:
             "sample": f"the first {distinct} inputs of the N=2^22 s=64 20 dB workload (the resident set), "
                       f"FP64 numpy oracle, {len(chunks)} single-threaded processes; value = inputs / the "
                       f"longest process time",
-            "single_thread_sft_per_s": single, "seconds": wall}
+            "single_thread_sft_per_s": single, "seconds": wall, **host_cpu()}
     print(f"[bench] oracle on {len(chunks)} cores: {base['value']:.2f} SFT/s ({single:.2f} per core)",
           file=sys.stderr, flush=True)
     return base, outs
@@ -359,6 +535,9 @@ def main():
     ap.add_argument("--no-phase", action="store_true", help="skip the phase-identification runs")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay run")
     ap.add_argument("--no-tune", action="store_true", help="skip the short-DFT path tuning sweep")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the further configurations (prime length, theory and dmsft4 presets)")
+    ap.add_argument("--extra-steps", type=int, default=5, help="timed batched calls per further configuration")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -374,9 +553,11 @@ def main():
     import siggen
 
     # the CPU baseline first: its worker processes are forked before any GPU use
-    cpu, oracle_out = None, {}
+    cpu, oracle_out, extra_ref = None, {}, {}
     if not args.no_cpu:
         cpu, oracle_out = cpu_baseline(args.distinct, min(args.cpu_workers, os.cpu_count() or 1))
+        if not args.no_extra:
+            extra_ref = oracle_jobs(EXTRA_WORKLOADS, min(args.cpu_workers, os.cpu_count() or 1))
 
     sft.require_device()
     torch.cuda.init()
@@ -456,7 +637,7 @@ def main():
     work = kernel_work(info)
     per_kernel = {}
     tpl = {}   # transforms per launch: a batch may be submitted as several pipelined groups
-    for name, (byts, flops) in work.items():
+    for name, (byts, flops, extra) in work.items():
         if kern[name]["avg_ms"] > 0:
             tpl[name] = B * args.steps / kern[name]["launches"]
             avg_s = kern[name]["avg_ms"] * 1e-3
@@ -464,20 +645,7 @@ def main():
                                 "hbm_frac": byts * tpl[name] / avg_s / 1e9 / HBM_PEAK_GBS,
                                 "transforms_per_launch": tpl[name]}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    roof = None
-    if dom in work and kern[dom]["avg_ms"] > 0:
-        byts, flops = work[dom]
-        ach = per_kernel[dom]["GBps"]
-        tr = measured_traffic(dom)
-        if tr and tr["transforms_per_launch"] != tpl[dom]:   # counters taken at another batch size
-            tr = None
-        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None,
-                "traffic_detail": tr,
-                "algorithmic_bytes_per_launch": byts * tpl[dom], "avg_launch_ms": kern[dom]["avg_ms"],
-                "transforms_per_launch": tpl[dom],
-                # a k_dft_mx launch of a split plan is two dispatches (smaller moduli, then the rest)
-                "dispatches_per_launch": 2 if dom == "k_dft_mx" and info.get("dft_split") else 1}
+    roof = roofline_of(dom, work, kern, tpl, info)
     gb = per_kernel.get("k_gather", {}).get("GBps", 0.0)
 
     # ---- accuracy against the oracle outputs of the CPU baseline
@@ -514,6 +682,13 @@ def main():
     graph = None if args.no_graph else graph_replay(sft, torch, plans, inputs, args.steps, stream)
     tuning = None if args.no_tune else tuning_sweep(sft, torch)
     phase = None if args.no_phase else phase_identification(sft, siggen, torch, stream, inputs, max(2, args.steps // 2))
+    extra = None
+    if not args.no_extra:
+        extra = {}
+        for spec in EXTRA_WORKLOADS:
+            extra[spec[0]] = workload_throughput(sft, siggen, torch, stream, spec, args.extra_steps,
+                                                 extra_ref.get(spec[0]))
+            torch.cuda.empty_cache()
 
     if args.calib_copy_mib > 0:   # a plain copy kernel of known size (reads and writes that many bytes)
         n = args.calib_copy_mib * 2 ** 20 // 4
@@ -549,6 +724,7 @@ def main():
         "phase_identification": phase,
         "graph_replay": graph,
         "tuning": tuning,
+        "further_configurations": extra,
     }
     print(json.dumps(out), flush=True)
 

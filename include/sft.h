@@ -18,6 +18,10 @@
  *     j = 0..N-1, i.e. numpy.fft.fft(f)[w mod N] / N.  The paper samples f at
  *     -pi + 2 pi j / N, so its fhat_w equals (-1)^w c_w.
  *   - Complex values are interleaved single precision (complex64: re, im).
+ *   - Device buffers passed to the execute calls must be aligned to their
+ *     element: f and out_coeffs to 8 bytes (complex64), out_freqs to 8 bytes
+ *     (int64), counts to 4 bytes; a misaligned pointer returns SFT_EINVAL
+ *     before anything is enqueued.  f need not be 16-byte aligned.
  *   - "stream" is a hipStream_t passed as void*; NULL is the null stream.
  *   - Every function returns an SFT_* status; no exception crosses the ABI.
  *     sft_last_error() gives the message of the calling thread's last failure.
@@ -158,17 +162,24 @@ SFT_API int sft_params_default(sft_params* p, int32_t preset);
 SFT_API int sft_plan_describe(int64_t N, int32_t s, const sft_params* p, sft_plan_info* out);
 
 /*
- * Create a plan on the current HIP device: derives the plan, uploads its
+ * Create a plan on the current HIP device: derives the plan and uploads its
  * tables (band phasors exp(-2 pi i (q_b i mod N)/N), DFT twiddles, CRT
- * constants) and allocates its workspace.  Synchronous.  On failure *out is
- * NULL and nothing is leaked.
+ * constants).  Synchronous.  The workspace of sft_execute is allocated by
+ * the plan's first sft_execute (a plan used only in batches never holds
+ * one).  On failure *out is NULL and nothing is leaked.
  */
 SFT_API int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p);
 
 SFT_API int sft_plan_get_info(const sft_plan_t plan, sft_plan_info* out);
 
-/* Device bytes the plan holds (tables + workspace); excludes f and outputs. */
+/* Device bytes the plan holds now: its tables, plus its sft_execute
+ * workspace once allocated; excludes f and outputs. */
 SFT_API int sft_plan_footprint(const sft_plan_t plan, size_t* bytes_device);
+
+/* Device workspace one transform of this plan needs (filtered samples,
+ * bins, heavy-bin tables, band results): the size of its sft_execute
+ * workspace and of its slice of a batch's workspace.  Host only. */
+SFT_API int sft_plan_workspace_bytes(const sft_plan_t plan, size_t* bytes);
 
 /*
  * One transform, enqueued on stream (asynchronous, no host synchronisation).
@@ -191,6 +202,26 @@ SFT_API int sft_execute(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_d
 SFT_API int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* f_dev,
                      int64_t* const* out_freqs_dev, void* const* out_coeffs_dev,
                      int32_t* out_counts_dev, void* stream);
+
+/*
+ * Device-side status of every transform of the last sft_execute_many on
+ * stream (Algorithm 1 per transform; the capacities are those of
+ * sft_plan_status).  Synchronises the stream; flags (host int32[count], may
+ * be NULL) receives each transform's flags.  count must equal that call's
+ * count.  Returns SFT_EOVERFLOW if any flag is set.
+ */
+SFT_API int sft_execute_many_status(void* stream, int32_t count, int32_t* flags);
+
+/*
+ * The workspace of sft_execute_many is owned by the library, one per
+ * (device, stream), and grows when a larger batch arrives (after the stream
+ * has drained).  reserve sizes it for batches of up to count transforms
+ * whose sft_plan_workspace_bytes sum to at most workspace_bytes, so that
+ * such calls allocate nothing; release frees the stream's workspace after
+ * its work has completed.
+ */
+SFT_API int sft_execute_many_reserve(void* stream, size_t workspace_bytes, int32_t count);
+SFT_API int sft_execute_many_release(void* stream);
 
 /*
  * Prepared batches: the transforms of sft_execute_many with their inputs and
@@ -217,11 +248,17 @@ SFT_API int sft_batch_create(sft_batch_t* out, const sft_plan_t* plans, int32_t 
 SFT_API int sft_batch_launch(sft_batch_t batch, void* stream);
 SFT_API int sft_batch_graph_launch(sft_batch_t batch, void* stream);
 SFT_API void sft_batch_destroy(sft_batch_t batch);
+/* Status flags of every transform of the batch's last launch (as
+ * sft_execute_many_status): synchronises, fills flags (host int32[count],
+ * may be NULL), returns SFT_EOVERFLOW if any is set. */
+SFT_API int sft_batch_status(sft_batch_t batch, int32_t* flags);
 
 /*
  * Synchronise with the plan's last sft_execute and return its device-side
  * status flags (0 = fine; bit 0: accepted-candidate list of a band overflowed;
- * bit 1: merge list overflowed).  Returns SFT_EOVERFLOW if any flag is set.
+ * bit 1: merge list overflowed).  Returns SFT_EOVERFLOW if any flag is set,
+ * SFT_EINVAL if the plan has not run sft_execute.  Batches report through
+ * sft_execute_many_status and sft_batch_status.
  */
 SFT_API int sft_plan_status(sft_plan_t plan, int32_t* flags);
 

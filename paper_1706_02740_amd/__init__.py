@@ -65,7 +65,9 @@ EXPORTED = [
     "sft_plan_footprint", "sft_execute", "sft_execute_many", "sft_plan_status",
     "sft_plan_fetch", "sft_plan_destroy", "sft_last_error", "sft_profile_enable",
     "sft_profile_reset", "sft_profile_read", "sft_batch_create", "sft_batch_launch",
-    "sft_batch_graph_launch", "sft_batch_destroy",
+    "sft_batch_graph_launch", "sft_batch_destroy", "sft_plan_workspace_bytes",
+    "sft_execute_many_status", "sft_execute_many_reserve", "sft_execute_many_release",
+    "sft_batch_status",
 ]
 
 
@@ -130,6 +132,11 @@ def load_library():
     lib.sft_batch_graph_launch.argtypes = [vp, vp]
     lib.sft_batch_destroy.argtypes = [vp]
     lib.sft_batch_destroy.restype = None
+    lib.sft_plan_workspace_bytes.argtypes = [vp, c.POINTER(c.c_size_t)]
+    lib.sft_execute_many_status.argtypes = [vp, c.c_int32, c.POINTER(c.c_int32)]
+    lib.sft_execute_many_reserve.argtypes = [vp, c.c_size_t, c.c_int32]
+    lib.sft_execute_many_release.argtypes = [vp]
+    lib.sft_batch_status.argtypes = [vp, c.POINTER(c.c_int32)]
     for name in EXPORTED:
         if name not in ("sft_plan_destroy", "sft_last_error", "sft_batch_destroy"):
             getattr(lib, name).restype = c.c_int
@@ -182,6 +189,35 @@ def describe(N: int, s: int, **params) -> dict:
     return _info_dict(info)
 
 
+def _check_input(f, N: int):
+    import torch
+    if not isinstance(f, torch.Tensor) or f.dtype != torch.complex64 or f.dim() != 1 or f.shape[0] != N \
+            or not f.is_cuda:
+        raise ValueError("f must be a complex64 cuda tensor of its plan's length")
+    if not f.is_contiguous():
+        raise ValueError("f must be contiguous")
+
+
+def _check_outputs(w, c, s: int, device, n=None):
+    """Caller-supplied outputs: int64[s] frequencies and complex64[s]
+    coefficients (and an int32 count tensor), contiguous, on f's device."""
+    import torch
+    for t, dt, name in ((w, torch.int64, "freqs"), (c, torch.complex64, "coefs")):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or t.dim() != 1 or t.shape[0] < s \
+                or t.device != device or not t.is_contiguous():
+            raise ValueError(f"output {name} must be a contiguous {dt} tensor of at least {s} entries on {device}")
+    if n is not None and (not isinstance(n, torch.Tensor) or n.dtype != torch.int32 or n.numel() < 1
+                          or n.device != device or not n.is_contiguous()):
+        raise ValueError(f"output count must be a contiguous int32 tensor on {device}")
+
+
+def _check_counts(counts, n: int, device):
+    import torch
+    if not isinstance(counts, torch.Tensor) or counts.dtype != torch.int32 or counts.numel() < n \
+            or counts.device != device or not counts.is_contiguous():
+        raise ValueError(f"counts must be a contiguous int32 tensor of at least {n} entries on {device}")
+
+
 def _stream_handle(stream) -> ctypes.c_void_p:
     import torch
     if stream is None:
@@ -208,8 +244,15 @@ class Plan:
         return self._h
 
     def footprint(self) -> int:
+        """Device bytes the plan holds now (tables; its sft_execute workspace once allocated)."""
         v = ctypes.c_size_t()
         _check(load_library().sft_plan_footprint(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def workspace_bytes(self) -> int:
+        """Device workspace one transform of this plan needs (alone or in a batch)."""
+        v = ctypes.c_size_t()
+        _check(load_library().sft_plan_workspace_bytes(self._h, ctypes.byref(v)))
         return int(v.value)
 
     def outputs(self, device=None):
@@ -222,12 +265,9 @@ class Plan:
     def execute(self, f, out=None, stream=None):
         """Enqueue one transform of the complex64 device tensor f (shape [N]).
         Returns (freqs int64[s], coefs complex64[s], count int32[1]) device tensors."""
-        import torch
-        if f.dtype != torch.complex64 or f.dim() != 1 or f.shape[0] != self.N or not f.is_cuda:
-            raise ValueError("f must be a complex64 cuda tensor of shape [N]")
-        if not f.is_contiguous():
-            raise ValueError("f must be contiguous")
+        _check_input(f, self.N)
         w, c, n = out if out is not None else self.outputs(f.device)
+        _check_outputs(w, c, self.s, f.device, n)
         _check(load_library().sft_execute(self._h, ctypes.c_void_p(f.data_ptr()),
                                           ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(c.data_ptr()),
                                           ctypes.c_void_p(n.data_ptr()), _stream_handle(stream)))
@@ -280,9 +320,13 @@ def execute_many(plans: Sequence[Plan], fs, outs=None, counts=None, stream=None)
                  torch.empty(p.s, dtype=torch.complex64, device=f.device)) for p, f in zip(plans, fs)]
     if counts is None:
         counts = torch.empty(n, dtype=torch.int32, device=fs[0].device if n else "cuda")
-    for p, f in zip(plans, fs):
-        if f.dtype != torch.complex64 or f.dim() != 1 or f.shape[0] != p.N or not f.is_cuda or not f.is_contiguous():
-            raise ValueError("every f must be a contiguous complex64 cuda tensor of its plan's length")
+    if len(outs) != n:
+        raise ValueError("plans and outs differ in length")
+    for p, f, o in zip(plans, fs, outs):
+        _check_input(f, p.N)
+        _check_outputs(o[0], o[1], p.s, f.device)
+    if n:
+        _check_counts(counts, n, fs[0].device)
     VP = ctypes.c_void_p * n
     hp = VP(*[p.handle.value for p in plans])
     hf = VP(*[f.data_ptr() for f in fs])
@@ -291,6 +335,27 @@ def execute_many(plans: Sequence[Plan], fs, outs=None, counts=None, stream=None)
     _check(load_library().sft_execute_many(hp, n, hf, hw, hc, ctypes.c_void_p(counts.data_ptr()),
                                            _stream_handle(stream)))
     return outs, counts
+
+
+def execute_many_status(stream, count: int) -> list:
+    """Per-transform status flags of the last execute_many on `stream`
+    (synchronises it); a nonzero entry is a device-side capacity overflow."""
+    flags = (ctypes.c_int32 * max(1, count))()
+    rc = load_library().sft_execute_many_status(_stream_handle(stream), int(count), flags)
+    if rc not in (SFT_OK, SFT_EOVERFLOW):
+        _check(rc)
+    return [int(flags[i]) for i in range(count)]
+
+
+def execute_many_reserve(stream, workspace_bytes: int, count: int):
+    """Size the library's workspace of `stream` for batches of up to `count`
+    transforms needing at most `workspace_bytes` (sum of workspace_bytes())."""
+    _check(load_library().sft_execute_many_reserve(_stream_handle(stream), int(workspace_bytes), int(count)))
+
+
+def execute_many_release(stream):
+    """Free the library's workspace of `stream` (after its work completes)."""
+    _check(load_library().sft_execute_many_release(_stream_handle(stream)))
 
 
 class Batch:
@@ -305,14 +370,17 @@ class Batch:
         if n < 1 or len(fs) != n:
             raise ValueError("plans and fs must be non-empty and of equal length")
         for p, f in zip(plans, fs):
-            if f.dtype != torch.complex64 or f.dim() != 1 or f.shape[0] != p.N or not f.is_cuda \
-                    or not f.is_contiguous():
-                raise ValueError("every f must be a contiguous complex64 cuda tensor of its plan's length")
+            _check_input(f, p.N)
         if outs is None:
             outs = [(torch.empty(p.s, dtype=torch.int64, device=f.device),
                      torch.empty(p.s, dtype=torch.complex64, device=f.device)) for p, f in zip(plans, fs)]
         if counts is None:
             counts = torch.empty(n, dtype=torch.int32, device=fs[0].device)
+        if len(outs) != n:
+            raise ValueError("plans and outs differ in length")
+        for p, f, o in zip(plans, fs, outs):
+            _check_outputs(o[0], o[1], p.s, f.device)
+        _check_counts(counts, n, fs[0].device)
         # the batch holds device pointers: keep the tensors and plans alive with it
         self.plans, self.fs, self.outs, self.counts = list(plans), list(fs), outs, counts
         VP = ctypes.c_void_p * n
@@ -329,6 +397,15 @@ class Batch:
     def graph_launch(self, stream=None):
         _check(load_library().sft_batch_graph_launch(self._h, _stream_handle(stream)))
         return self.outs, self.counts
+
+    def status(self) -> list:
+        """Per-transform status flags of the last launch (synchronises)."""
+        n = len(self.plans)
+        flags = (ctypes.c_int32 * n)()
+        rc = load_library().sft_batch_status(self._h, flags)
+        if rc not in (SFT_OK, SFT_EOVERFLOW):
+            _check(rc)
+        return [int(flags[i]) for i in range(n)]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

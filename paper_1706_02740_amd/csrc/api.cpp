@@ -331,13 +331,16 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     e = hipMemcpy(pl->ddesc, &d, sizeof(SigDesc), hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(descriptor)"); }
 
-    // ---- workspace of sft_execute
+    // ---- the workspace of sft_execute is allocated by the plan's first sft_execute
     pl->wl = workspace_layout(info);
-    e = hipMalloc(&pl->ws, pl->wl.total);
-    if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(workspace) failed"); }
-    pl->ws_io = carve(pl->ws, pl->wl);
-    pl->footprint = tbytes + sizeof(SigDesc) + pl->wl.total;
+    pl->footprint = tbytes + sizeof(SigDesc);
     *out = pl;
+    return SFT_OK;
+}
+
+int sft_plan_workspace_bytes(const sft_plan_t plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(SFT_EINVAL, "NULL argument");
+    *bytes = plan->wl.total;
     return SFT_OK;
 }
 
@@ -495,9 +498,19 @@ struct BatchShape {
     size_t ws_total = 0;
     size_t lds[SFT_KERNEL_COUNT] = {};
     bool used[SFT_KERNEL_COUNT] = {};   // some plan of the batch launches kernel k
-    size_t m_desc = 0, m_io = 0, m_pre = 0, meta_total = 0;
+    size_t m_desc = 0, m_io = 0, m_pre = 0, m_status = 0, meta_total = 0;
     bool one_plan = true;
 };
+
+// The kernels read f as 8-byte complex values (16-byte pieces where the
+// address allows) and write 8-byte frequencies and coefficients.
+int check_alignment(const void* f, const void* w, const void* c, const void* n) {
+    if (((uintptr_t)f & 7) != 0) return fail(SFT_EINVAL, "f must be 8-byte aligned (complex64)");
+    if (((uintptr_t)w & 7) != 0) return fail(SFT_EINVAL, "out_freqs must be 8-byte aligned (int64)");
+    if (((uintptr_t)c & 7) != 0) return fail(SFT_EINVAL, "out_coeffs must be 8-byte aligned (complex64)");
+    if (((uintptr_t)n & 3) != 0) return fail(SFT_EINVAL, "out_count must be 4-byte aligned (int32)");
+    return SFT_OK;
+}
 
 int batch_shape(const sft_plan_t* plans, int32_t count, const void* const* f_dev, int64_t* const* out_freqs_dev,
                 void* const* out_coeffs_dev, int dev, BatchShape& B) {
@@ -506,6 +519,7 @@ int batch_shape(const sft_plan_t* plans, int32_t count, const void* const* f_dev
     for (int i = 0; i < count; ++i) {
         const sft_plan_s* p = plans[i];
         if (!p || !f_dev[i] || !out_freqs_dev[i] || !out_coeffs_dev[i]) return fail(SFT_EINVAL, "NULL entry");
+        if (const int rc = check_alignment(f_dev[i], out_freqs_dev[i], out_coeffs_dev[i], nullptr)) return rc;
         if (p->device != dev) return fail(SFT_EINVAL, "plan belongs to another device");
         B.one_plan &= p == plans[0];
         B.wsoff[i] = B.ws_total;
@@ -530,15 +544,22 @@ int batch_shape(const sft_plan_t* plans, int32_t count, const void* const* f_dev
     B.m_desc = al(sizeof(void*) * count);
     B.m_io = al(sizeof(IoDesc) * count);
     B.m_pre = al(sizeof(int32_t) * (count + 1));
-    B.meta_total = B.m_desc + B.m_io + SFT_KERNEL_COUNT * B.m_pre;
+    B.m_status = al(sizeof(int32_t) * count);
+    B.meta_total = B.m_desc + B.m_io + SFT_KERNEL_COUNT * B.m_pre + B.m_status;
     return SFT_OK;
 }
 
-// The host image of the descriptor tables (hs, meta_total bytes) for the
-// workspace at ws; blocks receives the grid size of every kernel.
+// Offset of the per-transform status words (int32[count]) in the descriptor tables.
+size_t status_offset(const BatchShape& B) { return B.m_desc + B.m_io + SFT_KERNEL_COUNT * B.m_pre; }
+
+// The host image of the descriptor tables (hs, meta_total bytes) that will
+// sit at dm on the device, for the workspace at ws; blocks receives the grid
+// size of every kernel.  Each transform's status word is the count-long array
+// at status_offset(B) of the tables (zero in the image), not its workspace slice.
 void batch_tables(const BatchShape& B, const sft_plan_t* plans, int32_t count, const void* const* f_dev,
                   int64_t* const* out_freqs_dev, void* const* out_coeffs_dev, int32_t* out_counts_dev, char* ws,
-                  char* hs, int blocks[SFT_KERNEL_COUNT]) {
+                  char* dm, char* hs, int blocks[SFT_KERNEL_COUNT]) {
+    memset(hs + status_offset(B), 0, sizeof(int32_t) * (size_t)count);
     const SigDesc** hdesc = reinterpret_cast<const SigDesc**>(hs);
     IoDesc* hio = reinterpret_cast<IoDesc*>(hs + B.m_desc);
     int32_t* hpre[SFT_KERNEL_COUNT];
@@ -554,6 +575,7 @@ void batch_tables(const BatchShape& B, const sft_plan_t* plans, int32_t count, c
         io.out_w = out_freqs_dev[i];
         io.out_c = static_cast<float2*>(out_coeffs_dev[i]);
         io.out_n = out_counts_dev ? out_counts_dev + i : nullptr;
+        io.status = reinterpret_cast<int32_t*>(dm + status_offset(B)) + i;
         hio[i] = io;
         for (int k = 0; k < SFT_KERNEL_COUNT; ++k) {
             hpre[k][i] = blocks[k];
@@ -593,6 +615,8 @@ struct Arena {
     size_t meta_bytes = 0;
     void* staging = nullptr;     // pinned host copy of meta
     hipEvent_t staged = nullptr; // the last upload from staging has been consumed
+    int32_t last_count = 0;      // transforms of the last call on this stream
+    char* last_status = nullptr; // their status words (device)
 };
 std::mutex g_arena_mu;
 std::map<std::pair<int, void*>, Arena*> g_arenas;
@@ -605,6 +629,59 @@ Arena* arena_for(int dev, hipStream_t st) {
     Arena* a = new Arena();
     g_arenas[key] = a;
     return a;
+}
+
+Arena* arena_find(int dev, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    auto it = g_arenas.find(std::make_pair(dev, (void*)st));
+    return it == g_arenas.end() ? nullptr : it->second;
+}
+
+Arena* arena_take(int dev, hipStream_t st) {   // removed from the map; the caller frees it
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    auto it = g_arenas.find(std::make_pair(dev, (void*)st));
+    if (it == g_arenas.end()) return nullptr;
+    Arena* a = it->second;
+    g_arenas.erase(it);
+    return a;
+}
+
+// Descriptor-table bytes of a batch of count transforms (as batch_shape lays them out).
+size_t meta_bytes_for(int32_t count) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return al(sizeof(void*) * count) + al(sizeof(IoDesc) * count) + SFT_KERNEL_COUNT * al(sizeof(int32_t) * (count + 1)) +
+           al(sizeof(int32_t) * count);
+}
+
+// Grow the arena to hold ws_total workspace bytes and meta_total table bytes
+// (after the stream has drained, since its buffers are replaced); no-op when
+// it already does.  Waits until the previous upload from the staging buffer
+// has been consumed.
+int arena_fit(Arena* ar, hipStream_t st, size_t ws_total, size_t meta_total) {
+    if (ar->staged) HIP_TRY(hipEventSynchronize(ar->staged), "hipEventSynchronize");
+    if (ar->ws_bytes >= ws_total && ar->meta_bytes >= meta_total && ar->staged) return SFT_OK;
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (ar->ws_bytes < ws_total) {
+        if (ar->ws) (void)hipFree(ar->ws);
+        ar->ws = nullptr;
+        ar->ws_bytes = 0;
+        if (hipMalloc(&ar->ws, ws_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch workspace) failed");
+        ar->ws_bytes = ws_total;
+    }
+    if (ar->meta_bytes < meta_total) {
+        if (ar->meta) (void)hipFree(ar->meta);
+        if (ar->staging) (void)hipHostFree(ar->staging);
+        ar->meta = nullptr;
+        ar->staging = nullptr;
+        ar->meta_bytes = 0;
+        ar->last_status = nullptr;
+        if (hipMalloc(&ar->meta, meta_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch meta) failed");
+        if (hipHostMalloc(&ar->staging, meta_total, hipHostMallocDefault) != hipSuccess)
+            return fail(SFT_ENOMEM, "hipHostMalloc(batch staging) failed");
+        ar->meta_bytes = meta_total;
+    }
+    if (!ar->staged) HIP_TRY(hipEventCreateWithFlags(&ar->staged, hipEventDisableTiming), "hipEventCreate");
+    return SFT_OK;
 }
 }  // namespace
 
@@ -638,7 +715,16 @@ int sft_profile_read(int32_t kernel, int64_t* launches, double* total_ms) {
 int sft_execute(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_dev, void* out_coeffs_dev,
                 int32_t* out_count_dev, void* stream) {
     if (!plan || !f_dev || !out_freqs_dev || !out_coeffs_dev) return fail(SFT_EINVAL, "NULL argument");
+    if (const int rc = check_alignment(f_dev, out_freqs_dev, out_coeffs_dev, out_count_dev)) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!plan->ws) {   // the plan's first transform: its workspace
+        if (hipMalloc(&plan->ws, plan->wl.total) != hipSuccess) {
+            plan->ws = nullptr;
+            return fail(SFT_ENOMEM, "hipMalloc(workspace) failed");
+        }
+        plan->ws_io = carve(plan->ws, plan->wl);
+        plan->footprint += plan->wl.total;
+    }
     BatchArgs a;
     memset(&a, 0, sizeof(a));
     a.desc_one = plan->ddesc;
@@ -665,35 +751,58 @@ int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* 
     if (rc != SFT_OK) return rc;
 
     Arena* ar = arena_for(dev, st);
-    if (ar->staged) HIP_TRY(hipEventSynchronize(ar->staged), "hipEventSynchronize");
-    if (ar->ws_bytes < B.ws_total || ar->meta_bytes < B.meta_total) {
-        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-        if (ar->ws_bytes < B.ws_total) {
-            if (ar->ws) (void)hipFree(ar->ws);
-            ar->ws = nullptr;
-            ar->ws_bytes = 0;
-            if (hipMalloc(&ar->ws, B.ws_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch workspace) failed");
-            ar->ws_bytes = B.ws_total;
-        }
-        if (ar->meta_bytes < B.meta_total) {
-            if (ar->meta) (void)hipFree(ar->meta);
-            if (ar->staging) (void)hipHostFree(ar->staging);
-            ar->meta = nullptr;
-            ar->staging = nullptr;
-            ar->meta_bytes = 0;
-            if (hipMalloc(&ar->meta, B.meta_total) != hipSuccess) return fail(SFT_ENOMEM, "hipMalloc(batch meta) failed");
-            if (hipHostMalloc(&ar->staging, B.meta_total, hipHostMallocDefault) != hipSuccess)
-                return fail(SFT_ENOMEM, "hipHostMalloc(batch staging) failed");
-            ar->meta_bytes = B.meta_total;
-        }
-        if (!ar->staged) HIP_TRY(hipEventCreateWithFlags(&ar->staged, hipEventDisableTiming), "hipEventCreate");
-    }
+    if (const int rc2 = arena_fit(ar, st, B.ws_total, B.meta_total)) return rc2;
     int blocks[SFT_KERNEL_COUNT];
     batch_tables(B, plans, count, f_dev, out_freqs_dev, out_coeffs_dev, out_counts_dev, static_cast<char*>(ar->ws),
-                 static_cast<char*>(ar->staging), blocks);
+                 static_cast<char*>(ar->meta), static_cast<char*>(ar->staging), blocks);
     HIP_TRY(hipMemcpyAsync(ar->meta, ar->staging, B.meta_total, hipMemcpyHostToDevice, st), "hipMemcpyAsync(meta)");
     HIP_TRY(hipEventRecord(ar->staged, st), "hipEventRecord");
+    ar->last_count = count;
+    ar->last_status = static_cast<char*>(ar->meta) + status_offset(B);
     return enqueue_batch(B, plans, count, static_cast<char*>(ar->meta), blocks, st, true);
+}
+
+int sft_execute_many_status(void* stream, int32_t count, int32_t* flags) {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    Arena* ar = arena_find(dev, st);
+    if (!ar || !ar->last_status) return fail(SFT_EINVAL, "no sft_execute_many has run on this stream");
+    if (count != ar->last_count) return fail(SFT_EINVAL, "count differs from the last sft_execute_many on this stream");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    std::vector<int32_t> v((size_t)count);
+    HIP_TRY(hipMemcpy(v.data(), ar->last_status, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost),
+            "hipMemcpy(status)");
+    bool any = false;
+    for (int i = 0; i < count; ++i) {
+        if (flags) flags[i] = v[i];
+        any |= v[i] != 0;
+    }
+    if (any) return fail(SFT_EOVERFLOW, "a device-side capacity was exceeded in some transform of the batch");
+    return SFT_OK;
+}
+
+int sft_execute_many_reserve(void* stream, size_t workspace_bytes, int32_t count) {
+    if (count < 0) return fail(SFT_EINVAL, "count must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    return arena_fit(arena_for(dev, st), st, workspace_bytes, meta_bytes_for(count));
+}
+
+int sft_execute_many_release(void* stream) {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    Arena* ar = arena_take(dev, st);
+    if (!ar) return SFT_OK;
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (ar->ws) (void)hipFree(ar->ws);
+    if (ar->meta) (void)hipFree(ar->meta);
+    if (ar->staging) (void)hipHostFree(ar->staging);
+    if (ar->staged) (void)hipEventDestroy(ar->staged);
+    delete ar;
+    return SFT_OK;
 }
 
 // --------------------------------------------------- prepared batches ----
@@ -740,7 +849,7 @@ int sft_batch_create(sft_batch_t* out, const sft_plan_t* plans, int32_t count, c
     }
     std::vector<char> hs(b->shape.meta_total, 0);
     batch_tables(b->shape, plans, count, f_dev, out_freqs_dev, out_coeffs_dev, out_counts_dev,
-                 static_cast<char*>(b->ws), hs.data(), b->blocks);
+                 static_cast<char*>(b->ws), static_cast<char*>(b->meta), hs.data(), b->blocks);
     const hipError_t e = hipMemcpy(b->meta, hs.data(), b->shape.meta_total, hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_batch_destroy(b); return hip_fail(e, "hipMemcpy(batch tables)"); }
     *out = b;
@@ -776,8 +885,24 @@ int sft_batch_graph_launch(sft_batch_t b, void* stream) {
     return SFT_OK;
 }
 
+int sft_batch_status(sft_batch_t b, int32_t* flags) {
+    if (!b) return fail(SFT_EINVAL, "NULL batch");
+    HIP_TRY(hipStreamSynchronize(b->last), "hipStreamSynchronize");
+    std::vector<int32_t> v((size_t)b->count);
+    HIP_TRY(hipMemcpy(v.data(), static_cast<char*>(b->meta) + status_offset(b->shape), sizeof(int32_t) * v.size(),
+                      hipMemcpyDeviceToHost), "hipMemcpy(status)");
+    bool any = false;
+    for (int i = 0; i < b->count; ++i) {
+        if (flags) flags[i] = v[i];
+        any |= v[i] != 0;
+    }
+    if (any) return fail(SFT_EOVERFLOW, "a device-side capacity was exceeded in some transform of the batch");
+    return SFT_OK;
+}
+
 int sft_plan_status(sft_plan_t plan, int32_t* flags) {
     if (!plan) return fail(SFT_EINVAL, "NULL plan");
+    if (!plan->ws) return fail(SFT_EINVAL, "the plan has not run sft_execute");
     HIP_TRY(hipStreamSynchronize(plan->last_stream), "hipStreamSynchronize");
     int32_t v = 0;
     HIP_TRY(hipMemcpy(&v, plan->ws_io.status, 4, hipMemcpyDeviceToHost), "hipMemcpy(status)");
@@ -788,6 +913,7 @@ int sft_plan_status(sft_plan_t plan, int32_t* flags) {
 
 int sft_plan_fetch(const sft_plan_t plan, int32_t what, void* dst, size_t bytes, size_t* bytes_needed) {
     if (!plan) return fail(SFT_EINVAL, "NULL plan");
+    if (!plan->ws) return fail(SFT_EINVAL, "the plan has not run sft_execute");
     const sft_plan_info& in = plan->info;
     const void* src = nullptr;
     size_t need = 0;

@@ -312,17 +312,21 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             w[KP + o] = e0 * d->gtap[KP + o] * rp;
             w[KP - o] = e0 * d->gtap[KP - o] * rn;
         }
+        // f is 8-byte aligned; ab = 1 when it is not 16-byte aligned (element
+        // e then starts a 16-byte piece iff e is odd)
+        const int64_t ab = (int64_t)(((uintptr_t)io.f >> 3) & 1);
         for (int sh = 0;; ++sh) {
         const int64_t jc = jp + sh;   // window centre
         GLOBAL float2* __restrict__ S = glb(sh ? io.S2 : io.S) + soff;
         float2 x[TAPS];
-        if ((jc - kappa >= 0) && (jc + kappa + 1 < N)) {
-            // the window in 16-byte-aligned pieces from the even index at or
-            // below its start: (TAPS + 1) / 2 loads, none crossing a 16-byte
+        const int64_t st0 = jc - kappa;
+        const int64_t par = (st0 + ab) & 1;   // the window's first element is the upper half of its piece
+        if ((st0 - par >= 0) && (st0 + TAPS < N)) {
+            // the window in 16-byte-aligned pieces from the piece holding its
+            // first element: (TAPS + 1) / 2 loads, none crossing a 16-byte
             // boundary, all within the window's lines (the extra value shares a
             // piece with the first or the last tap); then a shift by the start's parity
-            const int64_t st0 = jc - kappa;
-            const GLOBAL pod_f4* w4 = (const GLOBAL pod_f4*)(f + (st0 & ~(int64_t)1));
+            const GLOBAL pod_f4* w4 = (const GLOBAL pod_f4*)(f + (st0 - par));
             static_assert(TAPS & 1, "2 kappa + 1 taps");
             float2 c[TAPS + 1];
 #pragma unroll
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             }
             // select by bit masks (a conditional select of c[i] and c[i + 1]
             // may become an indexed access that puts c in scratch memory)
-            const uint32_t m = 0u - (uint32_t)(st0 & 1);
+            const uint32_t m = 0u - (uint32_t)par;
 #pragma unroll
             for (int i = 0; i < TAPS; ++i) {   // in place: c[i + 1] is read before it is replaced
                 c[i].x = __uint_as_float((__float_as_uint(c[i].x) & ~m) | (__float_as_uint(c[i + 1].x) & m));

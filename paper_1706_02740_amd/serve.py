@@ -2,16 +2,22 @@
 
 Requests (a plan, a resident complex64 input, an arrival time) are admitted
 by device-memory footprint: a request needs its plan's per-transform
-workspace in the batch arena, and the requests in flight may hold at most
-`budget_bytes` of it.  Whenever an executor slot is free, everything
-admitted and waiting goes out as one `sft_execute_many` batch (at most
-`max_batch` transforms); requests that arrive while batches run wait for the
-next free slot, so their work overlaps the batches already on the device.
-A request whose footprint alone exceeds the budget is rejected.
+workspace in the batch workspace plus its outputs, and the requests in
+flight may hold at most `budget_bytes` of it.  Whenever an executor slot is
+free, everything admitted and waiting goes out as one `sft_execute_many`
+batch (at most `max_batch` transforms, and at most `slot_budget` bytes when
+the slots' workspaces are sized up front); requests that arrive while
+batches run wait for the next free slot, so their work overlaps the batches
+already on the device.  A request whose footprint alone exceeds the budget
+(or a slot) is rejected.
 
 The executor is pluggable: `GpuExecutor` runs each batch on its own HIP
-stream (default priority) and detects completion with an event; any object
-with the same three methods (launch, done, finish) can stand in for it.
+stream (default priority), each stream with the library's batch workspace
+reserved once for `reserve_bytes` (so the device memory of serving is the
+slots' reservations, and no batch allocates), and detects completion with
+an event; any object with the same three methods (launch, done, finish) can
+stand in for it.  A transform whose device-side capacities overflowed gets
+an error message and its (still filled) outputs.
 """
 from __future__ import annotations
 
@@ -41,15 +47,20 @@ class Request:
 class GpuExecutor:
     """One `sft_execute_many` per batch, each on its own stream."""
 
-    def __init__(self, slots: int = 2):
+    def __init__(self, slots: int = 2, reserve_bytes: int = 0, max_batch: int = 256):
         import torch
 
-        from . import execute_many
+        from . import execute_many, execute_many_release, execute_many_reserve, execute_many_status
         self._torch = torch
         self._execute_many = execute_many
+        self._status = execute_many_status
+        self._release = execute_many_release
         self.slots = slots
         self._streams = [torch.cuda.Stream() for _ in range(slots)]   # default priority
         self._busy = [False] * slots
+        if reserve_bytes:
+            for st in self._streams:
+                execute_many_reserve(st, reserve_bytes, max_batch)
 
     def free_slot(self) -> Optional[int]:
         for i, b in enumerate(self._busy):
@@ -81,23 +92,33 @@ class GpuExecutor:
     def finish(self, handle, batch: list) -> None:
         i, ev, outs, counts = handle
         ev.synchronize()
+        flags = self._status(self._streams[i], len(batch))
         for k, r in enumerate(batch):
             r.result = (outs[k][0], outs[k][1], counts[k:k + 1])
+            if flags[k]:
+                r.error = f"device-side capacity exceeded (status flags {flags[k]})"
         self._busy[i] = False
+
+    def close(self) -> None:
+        """Free the slots' batch workspaces (waits for their work)."""
+        for st in self._streams:
+            self._release(st)
 
 
 def footprint_bytes(plan) -> int:
-    """Device bytes charged to one in-flight transform of `plan`: the plan's
-    footprint (its workspace, which is also the transform's slice of the batch
-    arena, and its tables) plus the outputs."""
-    return int(plan.footprint()) + 16 * int(plan.s)
+    """Device bytes charged to one in-flight transform of `plan`: its slice
+    of the batch workspace plus its outputs (int64 and complex64 per slot, an
+    int32 count).  The plan's tables are resident for as long as the plan
+    and are not charged per request."""
+    return int(plan.workspace_bytes()) + 16 * int(plan.s) + 4
 
 
 class Server:
     def __init__(self, executor, budget_bytes: int, max_batch: int = 256,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, slot_budget: Optional[int] = None):
         self.ex = executor
         self.budget = int(budget_bytes)
+        self.slot_budget = self.budget if slot_budget is None else min(int(slot_budget), self.budget)
         self.max_batch = int(max_batch)
         self.clock = clock
         self.waiting = collections.deque()
@@ -110,7 +131,7 @@ class Server:
         self.max_held = 0
 
     def submit(self, r: Request) -> bool:
-        if r.nbytes > self.budget:
+        if r.nbytes > self.slot_budget:
             r.error = "footprint exceeds the serving budget"
             self.rejected.append(r)
             return False
@@ -141,9 +162,12 @@ class Server:
             return 0
         batch = []
         held = self.held
-        while self.waiting and len(batch) < self.max_batch and held + self.waiting[0].nbytes <= self.budget:
+        in_batch = 0
+        while self.waiting and len(batch) < self.max_batch and held + self.waiting[0].nbytes <= self.budget \
+                and in_batch + self.waiting[0].nbytes <= self.slot_budget:
             r = self.waiting.popleft()
             held += r.nbytes
+            in_batch += r.nbytes
             batch.append(r)
         if not batch:
             return 0

@@ -17,15 +17,37 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_algorithmic_bytes_of_the_headline():
     """N = 2^22, s = 64: M = 43,648 nodes per band, Q = 16 bands, 13 taps.
     The gather reads 13 complex64 per node and writes Q samples per node; the
-    short DFTs read and write every sample once."""
+    short DFTs read every sample once (5.59 MB per transform).  Their full
+    write of the bins is overhead: the method reads bins only at the heavy
+    ones and at accepted candidates."""
     info = sft.describe(2 ** 22, 64)
     assert info["M"] == 43_648 and info["Q"] == 16
     work = bench.kernel_work(info)
-    gather_bytes, gather_flops = work["k_gather"]
+    gather_bytes, gather_flops, gather_extra = work["k_gather"]
     assert gather_bytes == 43_648 * 13 * 8 + 16 * 43_648 * 8          # 4.54 MB + 5.59 MB
-    assert gather_flops == 16 * 43_648 * 13 * 8
-    dft_bytes, _ = work["k_dft_mx"]
-    assert dft_bytes == 2 * 16 * 43_648 * 8 == work["k_dft"][0]
+    assert gather_flops == 16 * 43_648 * 13 * 8 and gather_extra == 0
+    dft_bytes, _, dft_extra = work["k_dft_mx"]
+    assert dft_bytes == 16 * 43_648 * 8 == work["k_dft"][0] == dft_extra
+
+
+def test_roofline_object_from_algorithmic_bytes():
+    """frac = algorithmic bytes per launch / mean launch time / 8 TB/s: 256
+    headline transforms' sample reads (1.430 GB) in 0.954 ms are 0.187 of
+    the peak; the E write is reported as overhead, not counted."""
+    info = sft.describe(2 ** 22, 64)
+    work = bench.kernel_work(info)
+    kern = {"k_dft_mx": {"launches": 20, "total_ms": 20 * 0.954, "avg_ms": 0.954}}
+    roof = bench.roofline_of("k_dft_mx", work, kern, {"k_dft_mx": 256.0}, info)
+    assert roof["algorithmic_bytes_per_launch"] == 256 * 16 * 43_648 * 8
+    assert roof["frac"] == pytest.approx(256 * 16 * 43_648 * 8 / 0.954e-3 / 8e12)
+    assert 0.18 < roof["frac"] < 0.19
+    assert roof["overhead_bytes_per_launch"] == roof["algorithmic_bytes_per_launch"]
+
+
+def test_host_cpu_description():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and 1 <= h["usable_cpus"] <= h["nproc"]
+    assert h["cpu_model"] is None or isinstance(h["cpu_model"], str)
 
 
 def _traffic_file(path, sha, fetch_kib, write_kib):

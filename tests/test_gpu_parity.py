@@ -83,19 +83,15 @@ def _okw(kw):
     return {k: v for k, v in kw.items() if k != "dft_path"}
 
 
-@pytest.mark.parametrize("name,N,s,snr,kw,seed", INTERMEDIATE_CASES, ids=[c[0] for c in INTERMEDIATE_CASES])
-def test_intermediates_match_oracle(gpu, name, N, s, snr, kw, seed):
-    say("case", name)
-    sig = siggen.sparse_signal(N, s, seed=seed, snr_db=snr)
-    f32 = sig.f32
-    plan = gpu.Plan(N, s, **kw)
-    op = _oplan(N, s, kw)
-    wg, cg = gpu_run(plan, f32)
+def check_intermediates(gpu, plan, op, f32, bands=None):
+    """Samples, bins and heavy sets of the plan's last execute against the
+    oracle's, block by block (every band, or the given ones; every modulus)."""
     S_all = plan.fetch(gpu.FETCH_SAMPLES)
     E_all = plan.fetch(gpu.FETCH_BINS)
     H_all = plan.fetch(gpu.FETCH_HEAVY)
     in_scale = float(np.max(np.abs(f32))) / np.sqrt(2 * np.pi)
-    for b in range(op.Q):
+    worst = 0.0
+    for b in (range(op.Q) if bands is None else bands):
         for j in range(op.K):
             So = oracle.filtered_samples(op, f32, b, j)
             Sg = gpu.samples_natural(plan, S_all, b, j)
@@ -114,12 +110,50 @@ def test_intermediates_match_oracle(gpu, name, N, s, snr, kw, seed):
                 thr = np.sort(mag)[::-1][op.T - 1]
                 for h in diff:
                     assert abs(mag[h] - thr) <= 3e-5 * escale, (b, j, h)
+            worst = max(worst, float(np.max(np.abs(Sg - So))) / scale)
+    return worst
+
+
+@pytest.mark.parametrize("name,N,s,snr,kw,seed", INTERMEDIATE_CASES, ids=[c[0] for c in INTERMEDIATE_CASES])
+def test_intermediates_match_oracle(gpu, name, N, s, snr, kw, seed):
+    say("case", name)
+    sig = siggen.sparse_signal(N, s, seed=seed, snr_db=snr)
+    f32 = sig.f32
+    plan = gpu.Plan(N, s, **kw)
+    op = _oplan(N, s, kw)
+    wg, cg = gpu_run(plan, f32)
+    check_intermediates(gpu, plan, op, f32)
     wo, co = oracle.sft(op, f32)
+    assert_same_result(wg, cg, wo, co)
+
+
+@pytest.mark.parametrize("name,N,s,snr,kw,bands", [
+    # the headline plan: K = 7 moduli (primes 37..61, h up to 30: both matrix-core M-tiles live)
+    ("headline_n2e22_s64_20db", 2 ** 22, 64, 20.0, {}, (0, 7, 15)),
+    # Theorem 4's preset at the headline length: kappa = 22, the widest window (45 taps), Q = 40;
+    # pins the uncompensated FP32 tap sums at 45 taps against the FP64 oracle
+    ("theory_n2e22_s64_20db", 2 ** 22, 64, 20.0, {"preset": 2}, (0, 19, 39)),
+])
+def test_full_size_intermediates_match_oracle(gpu, name, N, s, snr, kw, bands):
+    """Element-wise samples, bins and heavy sets at full-size plans, for three
+    bands and every modulus, then the end-to-end result."""
+    say("case", name)
+    sig = siggen.sparse_signal(N, s, seed=4, snr_db=snr)
+    plan = gpu.Plan(N, s, **kw)
+    op = _oplan(N, s, kw)
+    wg, cg = gpu_run(plan, sig.f32)
+    worst = check_intermediates(gpu, plan, op, sig.f32, bands)
+    say(name, "largest sample error / block scale", worst)
+    wo, co = oracle.sft(op, sig.f32)
     assert_same_result(wg, cg, wo, co)
 
 
 END_TO_END = [
     ("plain_n2e14_s8", 2 ** 14, 8, None, "unit", {}, range(0, 6)),
+    # the serving mix's low end of SNR and its large s, against the oracle
+    ("n2e16_s40_0db", 2 ** 16, 40, 0.0, "unit", {}, range(0, 3)),
+    ("n2e18_s512_20db", 2 ** 18, 512, 20.0, "unit", {}, range(0, 1)),
+    ("n2e20_s1024_10db", 2 ** 20, 1024, 10.0, "unit", {}, range(0, 1)),
     ("ragged_n2621441_s200_30db", 5 * 2 ** 19 + 1, 200, 30.0, "unit", {}, range(0, 1)),
     ("n3x2e20_s16_30db", 3 * 2 ** 20, 16, 30.0, "unit", {}, range(0, 1)),
     ("n2e18_s256_30db", 2 ** 18, 256, 30.0, "unit", {}, range(0, 1)),
@@ -278,11 +312,20 @@ def test_serving_mix_results_equal_alone(gpu):
     reqs[5].nbytes = budget + 1
     torch.cuda.synchronize()
     say("serving", len(reqs), "requests,", len(plans), "plans")
-    srv = serve.Server(serve.GpuExecutor(slots=2), budget_bytes=budget, max_batch=16)
+    free0 = torch.cuda.mem_get_info()[0]
+    ex = serve.GpuExecutor(slots=2, reserve_bytes=budget // 2, max_batch=16)
+    srv = serve.Server(ex, budget_bytes=budget, max_batch=16, slot_budget=budget // 2)
     serve.run_trace(srv, reqs)
     torch.cuda.synchronize()
+    # device memory of the run: the two slots' reserved workspaces plus the
+    # outputs (torch's allocator rounds each to its 2 MB blocks)
+    used = free0 - torch.cuda.mem_get_info()[0]
+    say("serving used", used, "bytes of device memory for a budget of", budget)
+    assert used <= budget + (64 << 20), used
+    ex.close()
     assert [r.rid for r in srv.rejected] == [5]
     assert len(srv.completed) == len(reqs) - 1
+    assert all(r.error is None for r in srv.completed)
     assert srv.max_inflight == 2 and srv.batches >= 4 and srv.max_held <= budget
     for r in srv.completed:
         w, c, n = r.plan.execute(r.f)
@@ -463,3 +506,82 @@ def test_matrix_core_moduli_split_rule(gpu):
     assert max(primes[:j1]) < min(primes[j1:]) and primes[j1 - 1] == 47
     assert gpu.Plan(2 ** 21, 32, dft_path=3).info["dft_split"] == 0
     assert gpu.Plan(2 ** 22, 64, dft_path=4).info["dft_split"] == 0
+
+
+@pytest.mark.parametrize("snr", [0.0, -10.0])
+def test_noise_protocol_shape_matches_oracle(gpu, snr):
+    """Section 5.4's shape (N = 2^22, s = 50) at the lowest SNRs of the noise
+    sweep: the GPU's FP32 decisions (heavy sets, votes) against the oracle's
+    FP64 ones, end to end, on three inputs per level."""
+    N, s = 2 ** 22, 50
+    plan = gpu.Plan(N, s)
+    op = _oplan(N, s, {})
+    for seed in range(3):
+        sig = siggen.sparse_signal(N, s, seed=600 + seed, snr_db=snr)
+        say("noise protocol vs oracle", snr, "dB, seed", seed)
+        wg, cg = gpu_run(plan, sig.f32)
+        wo, co = oracle.sft(op, sig.f32)
+        rel = assert_same_result(wg, cg, wo, co)
+        say("  supports equal, rel-l2", rel, "; true support found:", set(wo.tolist()) == set(sig.freqs.tolist()))
+
+
+def test_batched_status_reports_overflow(gpu):
+    """Device-side capacity overflows are reported per transform by the
+    batched calls: a plan whose every bin is heavy (heavy_T above the DFT
+    lengths, s = 2: an accept capacity of 16 against hundreds of accepted
+    candidates per band) sets its transform's flag; the other transforms of
+    the batch stay clear.  The same through a prepared batch and a plain call."""
+    N = 2 ** 14
+    over = gpu.Plan(N, 2, heavy_T=100_000)
+    ok = gpu.Plan(N, 8)
+    f = dev(siggen.sparse_signal(N, 8, seed=3, snr_db=20.0).f32)
+    st = torch.cuda.current_stream()
+    say("batched status")
+    gpu.execute_many([ok, over, ok], [f, f, f])
+    flags = gpu.execute_many_status(st, 3)
+    assert flags[0] == 0 and flags[2] == 0 and (flags[1] & 1), flags
+    gpu.execute_many([ok, ok], [f, f])
+    assert gpu.execute_many_status(st, 2) == [0, 0]
+    with pytest.raises(gpu.SftError):
+        gpu.execute_many_status(st, 3)            # not the count of the last call
+    b = gpu.Batch([over, ok], [f, f])
+    b.launch()
+    fl = b.status()
+    assert (fl[0] & 1) and fl[1] == 0, fl
+    b.close()
+    over.execute(f)
+    torch.cuda.synchronize()
+    assert over.status() & 1
+    ok.execute(f)
+    torch.cuda.synchronize()
+    assert ok.status() == 0
+
+
+def test_input_at_8_byte_offset(gpu):
+    """f need only be 8-byte aligned: a contiguous complex64 view one element
+    into a buffer (8 modulo 16 bytes) gives the outputs of the aligned copy
+    bit for bit, plain and batched; a pointer off by 4 bytes is refused
+    before anything runs."""
+    import ctypes
+    for N, s, kw in ((2 ** 16, 40, {}), (100_003, 20, {}), (2 ** 14, 8, {"preset": 2}), (2 ** 14, 8, {"preset": 1})):
+        sg = siggen.sparse_signal(N, s, seed=31, snr_db=20.0)
+        fa = dev(sg.f32)
+        buf = torch.zeros(N + 1, dtype=torch.complex64, device="cuda")
+        buf[1:] = fa
+        fo = buf[1:]
+        assert fo.data_ptr() % 16 == 8 and fa.data_ptr() % 16 == 0
+        plan = gpu.Plan(N, s, **kw)
+        say("8-byte offset", N, s, kw)
+        ra = [t.cpu().numpy().copy() for t in plan.execute(fa)]
+        ro = [t.cpu().numpy().copy() for t in plan.execute(fo)]
+        for x, y in zip(ra, ro):
+            assert np.array_equal(x, y)
+        outs, counts = gpu.execute_many([plan, plan], [fo, fa])
+        torch.cuda.synchronize()
+        for o in outs:
+            assert np.array_equal(o[0].cpu().numpy(), ra[0]) and np.array_equal(o[1].cpu().numpy(), ra[1])
+    w, c, n = plan.outputs()
+    lib = gpu.load_library()
+    rc = lib.sft_execute(plan.handle, ctypes.c_void_p(fa.data_ptr() + 4), ctypes.c_void_p(w.data_ptr()),
+                         ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(n.data_ptr()), None)
+    assert rc == gpu.SFT_EINVAL and b"aligned" in lib.sft_last_error()

@@ -125,5 +125,10 @@ def test_batched_phase_and_residue_plans_equal_plain(gpu):
 
 def test_phase_fetch_rejected_for_residue_plans(gpu):
     plan = gpu.Plan(2 ** 14, 8)
+    with pytest.raises(gpu.SftError):          # no sft_execute has run: no workspace yet
+        plan.fetch(gpu.FETCH_BINS)
+    plan.execute(torch.from_numpy(siggen.sparse_signal(2 ** 14, 8, seed=1).f32).cuda())
+    torch.cuda.synchronize()
+    assert plan.fetch(gpu.FETCH_BINS).size == plan.info["Q"] * plan.info["M"]
     with pytest.raises(gpu.SftError):
         plan.fetch(gpu.FETCH_BINS_SHIFTED)

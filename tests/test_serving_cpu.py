@@ -88,3 +88,18 @@ def test_admission_by_footprint():
     assert len(srv.completed) == 5
     assert srv.max_held <= 50
     assert all(len(b) <= 2 for b in ex.launched)              # at most two 25-byte requests fit
+
+
+def test_slot_budget_bounds_each_batch():
+    """With the slots' workspaces sized up front (slot_budget = budget /
+    slots), no batch holds more than one slot's bytes, and a request larger
+    than a slot is rejected."""
+    reqs = make_requests(8, nbytes=20)
+    reqs[3].nbytes = 45                                       # fits the budget, not a slot
+    ex = FakeExecutor(slots=2, polls=2)
+    srv = Server(ex, budget_bytes=80, max_batch=8, clock=Tick(), slot_budget=40)
+    run_trace(srv, reqs, t0=0.0)
+    assert [r.rid for r in srv.rejected] == [3]
+    assert len(srv.completed) == 7 and srv.max_held <= 80
+    sizes = {r.rid: r.nbytes for r in reqs}
+    assert all(sum(sizes[i] for i in b) <= 40 for b in ex.launched)
