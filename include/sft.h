@@ -194,6 +194,26 @@ SFT_API int sft_execute(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_d
                 void* out_coeffs_dev, int32_t* out_count_dev, void* stream);
 
 /*
+ * sft_execute for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as sft_execute, with the workspace taken from a
+ * fixed per-device scratch array of the library (64 MiB; each device the
+ * library runs on holds it until the process ends) instead of the plan's own.
+ * Calls no hipMalloc, hipFree or other allocating routine, and records no
+ * per-kernel timing events.  Arguments as sft_execute; the plan must have been
+ * created on the current device.  Returns SFT_EINVAL, before anything is
+ * enqueued, when sft_plan_workspace_bytes of the plan exceeds 64 MiB (the
+ * headline N = 2^22, s = 64 plan needs 11.5 MB).  Every call on a device
+ * shares that device's scratch and leaves its contents behind: calls that
+ * overlap on one device (different streams, or host threads, without
+ * ordering between them) race and give wrong results; order them on one
+ * stream.  sft_plan_status reads the call's flags from the scratch, valid
+ * until the next call that uses it; sft_plan_fetch does not see it.
+ */
+SFT_API int sft_execute_noalloc(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_dev,
+                                void* out_coeffs_dev, int32_t* out_count_dev, void* stream);
+
+/*
  * count transforms in one batched launch sequence; plans may differ in N and s
  * and the same plan may appear several times.  Arrays are host arrays of
  * device pointers, one entry per transform; out_counts_dev is a device
@@ -254,7 +274,7 @@ SFT_API void sft_batch_destroy(sft_batch_t batch);
 SFT_API int sft_batch_status(sft_batch_t batch, int32_t* flags);
 
 /*
- * Synchronise with the plan's last sft_execute and return its device-side
+ * Synchronise with the plan's last sft_execute (or sft_execute_noalloc) and return its device-side
  * status flags (0 = fine; bit 0: accepted-candidate list of a band overflowed;
  * bit 1: merge list overflowed).  Returns SFT_EOVERFLOW if any flag is set,
  * SFT_EINVAL if the plan has not run sft_execute.  Batches report through

@@ -67,7 +67,7 @@ EXPORTED = [
     "sft_profile_reset", "sft_profile_read", "sft_batch_create", "sft_batch_launch",
     "sft_batch_graph_launch", "sft_batch_destroy", "sft_plan_workspace_bytes",
     "sft_execute_many_status", "sft_execute_many_reserve", "sft_execute_many_release",
-    "sft_batch_status",
+    "sft_batch_status", "sft_execute_noalloc",
 ]
 
 
@@ -115,6 +115,7 @@ def load_library():
     lib.sft_plan_get_info.argtypes = [vp, c.POINTER(PlanInfo)]
     lib.sft_plan_footprint.argtypes = [vp, c.POINTER(c.c_size_t)]
     lib.sft_execute.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.sft_execute_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.sft_execute_many.argtypes = [c.POINTER(vp), c.c_int32, c.POINTER(vp), c.POINTER(vp),
                                      c.POINTER(vp), vp, vp]
     lib.sft_plan_status.argtypes = [vp, c.POINTER(c.c_int32)]
@@ -271,6 +272,18 @@ class Plan:
         _check(load_library().sft_execute(self._h, ctypes.c_void_p(f.data_ptr()),
                                           ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(c.data_ptr()),
                                           ctypes.c_void_p(n.data_ptr()), _stream_handle(stream)))
+        return w, c, n
+
+    def execute_noalloc(self, f, out, stream=None):
+        """As execute(), through sft_execute_noalloc: the library allocates
+        nothing (its per-device scratch is the workspace); the caller supplies
+        the outputs (freqs int64[s], coefs complex64[s], count int32[1])."""
+        _check_input(f, self.N)
+        w, c, n = out
+        _check_outputs(w, c, self.s, f.device, n)
+        _check(load_library().sft_execute_noalloc(self._h, ctypes.c_void_p(f.data_ptr()),
+                                                  ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                                                  ctypes.c_void_p(n.data_ptr()), _stream_handle(stream)))
         return w, c, n
 
     def status(self) -> int:

@@ -47,6 +47,7 @@ struct sft_plan_s {
     MxSplit mxs;            // the matrix-core short DFTs in two launches (mxs.j1 > 0)
     int device = 0;
     hipStream_t last_stream = nullptr;
+    int32_t* last_status = nullptr;   // status word of the last single transform (own workspace or scratch)
 };
 
 static IoDesc carve(void* base, const WorkspaceLayout& wl) {
@@ -735,7 +736,37 @@ int sft_execute(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_dev, void
     a.io_one.out_n = out_count_dev;
     a.nsig = 1;
     plan->last_stream = st;
+    plan->last_status = plan->ws_io.status;
     return enqueue(a, plan->blocks, plan->lds, nullptr, st, nullptr, &plan->mxs);
+}
+
+int sft_execute_noalloc(sft_plan_t plan, const void* f_dev, int64_t* out_freqs_dev, void* out_coeffs_dev,
+                        int32_t* out_count_dev, void* stream) {
+    if (!plan || !f_dev || !out_freqs_dev || !out_coeffs_dev) return fail(SFT_EINVAL, "NULL argument");
+    if (const int rc = check_alignment(f_dev, out_freqs_dev, out_coeffs_dev, out_count_dev)) return rc;
+    if (plan->wl.total > sft::kScratchBytes)
+        return fail(SFT_EINVAL, "the plan's workspace (" + std::to_string(plan->wl.total) +
+                                    " bytes) exceeds the no-alloc scratch (" + std::to_string(sft::kScratchBytes) +
+                                    " bytes); use sft_execute");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != plan->device) return fail(SFT_EINVAL, "the plan was created on another device");
+    void* ws = nullptr;
+    HIP_TRY(sft::scratch_address(dev, &ws), "hipGetSymbolAddress(scratch)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.desc_one = plan->ddesc;
+    a.io_one = carve(ws, plan->wl);   // the status word is cleared by the first kernel, nothing else is read first
+    a.io_one.f = static_cast<const float2*>(f_dev);
+    a.io_one.out_w = out_freqs_dev;
+    a.io_one.out_c = static_cast<float2*>(out_coeffs_dev);
+    a.io_one.out_n = out_count_dev;
+    a.nsig = 1;
+    plan->last_stream = st;
+    plan->last_status = a.io_one.status;
+    // no per-kernel timing events: creating them may allocate
+    return enqueue(a, plan->blocks, plan->lds, nullptr, st, nullptr, &plan->mxs, false);
 }
 
 int sft_execute_many(const sft_plan_t* plans, int32_t count, const void* const* f_dev,
@@ -902,10 +933,10 @@ int sft_batch_status(sft_batch_t b, int32_t* flags) {
 
 int sft_plan_status(sft_plan_t plan, int32_t* flags) {
     if (!plan) return fail(SFT_EINVAL, "NULL plan");
-    if (!plan->ws) return fail(SFT_EINVAL, "the plan has not run sft_execute");
+    if (!plan->last_status) return fail(SFT_EINVAL, "the plan has not run sft_execute");
     HIP_TRY(hipStreamSynchronize(plan->last_stream), "hipStreamSynchronize");
     int32_t v = 0;
-    HIP_TRY(hipMemcpy(&v, plan->ws_io.status, 4, hipMemcpyDeviceToHost), "hipMemcpy(status)");
+    HIP_TRY(hipMemcpy(&v, plan->last_status, 4, hipMemcpyDeviceToHost), "hipMemcpy(status)");
     if (flags) *flags = v;
     if (v != 0) return fail(SFT_EOVERFLOW, "a device-side capacity was exceeded");
     return SFT_OK;

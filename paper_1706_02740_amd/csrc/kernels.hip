@@ -19,6 +19,7 @@
 // (or, for a batch of one plan, a division) maps blockIdx.x to (signal, local
 // block).  A k_dft launch may cover a range of the moduli only.
 #include <algorithm>
+#include <mutex>
 
 #include "sft_internal.h"
 
@@ -2392,6 +2393,31 @@ hipError_t configure_kernels(int max_lds) {
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds - static_lds) != hipSuccess)
             (void)hipGetLastError();
     }
+    return hipSuccess;
+}
+
+// Workspace of sft_execute_noalloc, for callers that cannot allocate device
+// memory: a fixed array in every device's copy of the code object, held until
+// the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol); it passes the device address
+// that hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
     return hipSuccess;
 }
 

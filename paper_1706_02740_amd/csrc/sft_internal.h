@@ -175,6 +175,11 @@ hipError_t launch_dft_cols_mx(const BatchArgs& a, int blocks, size_t lds, hipStr
 hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_merge(const BatchArgs& a, int blocks, hipStream_t st);
 hipError_t configure_kernels(int max_lds);
+// The no-alloc workspace: kScratchBytes per device, its device address on
+// device dev (the current device; looked up on the first call per device).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int dev, void** out);
 size_t identify_lds_bytes(const SigDesc& d, bool bitmap);   // with or without the heavy-bin bitmaps
 size_t merge_lds_bytes();
 
