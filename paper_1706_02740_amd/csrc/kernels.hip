@@ -528,6 +528,14 @@ constexpr int brev_const(int i, int bits) {
 }
 constexpr int log2_const(int r) { return r <= 1 ? 0 : 1 + log2_const(r / 2); }
 
+// Column swizzle of the matrix-core kernel's block in LDS: complex value c of
+// row r sits at c ^ swz_col(r).  Rows a multiple of 4 apart keep their
+// columns, rows 1, 2, 3 apart move by 8, 16, 24 complex values (64 to 192
+// bytes), so the p-point step's B operands (four consecutive rows, the same
+// 16 floats in each) fall in four different groups of 16 banks, and so do the
+// row FFT's stores (eight consecutive rows, the same 8 complex values in each).
+__device__ __forceinline__ int swz_col(int row) { return (row & 3) << 3; }
+
 // v <- DFT_R(v): X_k = sum_n v_n exp(-2 pi i n k / R), radix-2 decimation in
 // time with compile-time twiddles (the bit reversal is a register renaming).
 template <int R>
@@ -567,8 +575,10 @@ __device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
 //   X[R2 k1 + k2] = sum_n1 Z[n1][k2] W_R1^(n1 k1)
 // Z sits in the row at k2 R1 + (n1 ^ f), f = (k2 + R2 (row & 1)) mod R1, so
 // that pass 2 reads R1 values per thread without LDS bank conflicts.
+// SWZ: the result X[k] of a row goes to position k ^ swz_col(row) instead of k
+// (the layout the matrix-core p-point step reads without bank conflicts).
 // tw: LDS exp(-2 pi i m / S), m < S.
-template <int NT, int R1, int R2, int ROWSMAX>
+template <int NT, int R1, int R2, int ROWSMAX, bool SWZ = false>
 __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
     constexpr int S = R1 * R2;
     constexpr int IT1 = (ROWSMAX * R1 + NT - 1) / NT;
@@ -628,9 +638,10 @@ __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
         if (item < rows * R2) {
             const int row = item >> L2;
             const int k2 = item & (R2 - 1);
-            float2* xr = buf + row * S + k2;
+            float2* xr = buf + row * S;
+            const int sw = SWZ ? swz_col(row) : 0;
 #pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) xr[k1 * R2] = y[it][k1];
+            for (int k1 = 0; k1 < R1; ++k1) xr[(k1 * R2 + k2) ^ sw] = y[it][k1];
         }
     }
     __syncthreads();
@@ -639,10 +650,11 @@ __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
 // Row FFTs: two register passes for s1 = 64 and 128 (at most ROWS128 and
 // ROWS64 rows), else the radix-2/4 LDS passes.  The in-LDS and the split
 // kernels take the same branch for a plan, so their results stay bitwise equal.
-template <int NT, int ROWS128, int ROWS64>
+template <int NT, int ROWS128, int ROWS64, bool SWZ = false>
 __device__ __forceinline__ void fft_rows(float2* buf, int rows, int s1, int lg, const float2* tw) {
-    if (s1 == 128 && rows <= ROWS128) fft_rows_2pass<NT, 16, 8, ROWS128>(buf, rows, tw);
-    else if (s1 == 64 && rows <= ROWS64) fft_rows_2pass<NT, 8, 8, ROWS64>(buf, rows, tw);
+    static_assert(!SWZ || (ROWS128 >= 64 && ROWS64 >= 64), "the swizzled layout needs the register passes");
+    if (s1 == 128 && rows <= ROWS128) fft_rows_2pass<NT, 16, 8, ROWS128, SWZ>(buf, rows, tw);
+    else if (s1 == 64 && rows <= ROWS64) fft_rows_2pass<NT, 8, 8, ROWS64, SWZ>(buf, rows, tw);
     else fft_rows_lds<NT>(buf, rows, s1, lg, tw);
 }
 
@@ -1028,17 +1040,102 @@ __device__ __forceinline__ float lane_pair(float v) {
 // FP32 16x16x4 MFMAs: M = 16 values of k, N = 16 floats (8 columns), K = 4
 // values of n.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
 // receives D[4 (l / 16) + r][l % 16] in register r.  Wave w owns the N-tiles
-// w + 8 t (t < ntw = s1 / 64) and the M-tiles m < mt = ceil((h + 1) / 16)
-// (at most NTW and MT).  bf: the block as floats.
-// At: the A operands in lane order ((st ATILES + m) 64 + lane, as the
-// plan's mxa and mxc tables), in LDS or global memory; an: on entry the
-// operands of step 0 (At[m 64 + lane]); each step's operands are loaded one
-// step ahead.
+// w + 8 t, t < NTW = s1 / 64, and the M-tiles m < MT = ceil((h + 1) / 16).
+// bf: the block as floats, columns swizzled by swz_col.  At: the A operands in
+// lane order ((st ATILES + m) 64 + lane, as the plan's mxa and mxc tables), in
+// LDS or global memory; an: on entry the operands of step 0
+// (At[m 64 + lane]); each step's A operands and the B operands (four LDS
+// reads per N-tile) are loaded one step ahead.  A lane's rows n and p - n
+// move by 4 per step, so their swizzle stays the same and the reads of the
+// steps before the last are fixed offsets from two addresses.
 __device__ __forceinline__ float2 load_a(const float2* p) { return *p; }
 __device__ __forceinline__ float2 load_a(const GLOBAL float2* p) { return ld2(p); }
 
 template <int MT, int NTW, int ATILES = kMxTiles, class AP>
-__device__ __forceinline__ void pfa_mfma(const float* bf, int s1, int p, int h, int mt, int ntw, AP At,
+__device__ __forceinline__ void pfa_mfma(const float* bf, int p, int h, AP At, float2 (&an)[kMxTiles],
+                                         mf4 (&Cm)[2][kMxTiles], mf4 (&Dm)[2][kMxTiles]) {
+    static_assert(MT <= ATILES && MT <= kMxTiles && NTW <= 2, "A operand tiles");
+    constexpr int RS = 128 * NTW;   // floats per row: s1 = 64 NTW
+    const int lane = (int)threadIdx.x & 63;
+    const int wid = (int)threadIdx.x >> 6;
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < NTW; ++t)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            Cm[t][m] = mf4{0.f, 0.f, 0.f, 0.f};
+            Dm[t][m] = mf4{0.f, 0.f, 0.f, 0.f};
+        }
+    const int steps = (h + 3) >> 2;   // <= kMxSteps
+    int col[NTW];                     // the lane's float column in each N-tile
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) col[t] = 16 * (wid + 8 * t) + li;
+    auto at = [&](int row, int t) { return row * RS + (col[t] ^ (2 * swz_col(row))); };
+    const int ra = 1 + lk, rb = p - 1 - lk;   // the lane's rows n and p - n at step 0
+    int oa[NTW], ob[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        oa[t] = at(ra, t);
+        ob[t] = at(rb, t);
+    }
+    // B operands of step st: rows n = 1 + 4 st + lk and p - n; in the last
+    // step rows past h are clamped into the block (their values are not used)
+    auto fetch = [&](int st, float (&va)[NTW], float (&vb)[NTW]) {
+        if (4 * st + 4 <= h) {   // every lane's n <= h (uniform)
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                va[t] = bf[oa[t] + st * 4 * RS];
+                vb[t] = bf[ob[t] - st * 4 * RS];
+            }
+        } else {
+            const int n = 1 + 4 * st + lk;
+            const int r1 = min(n, p - 1), r2 = max(p - n, 0);
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                va[t] = bf[at(r1, t)];
+                vb[t] = bf[at(r2, t)];
+            }
+        }
+    };
+    float xa[NTW], xb[NTW];
+    fetch(0, xa, xb);
+#pragma unroll
+    for (int st = 0; st < kMxSteps; ++st) {
+        if (st >= steps) break;
+        float2 av[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) av[m] = an[m];
+        float ya[NTW], yb[NTW];
+        if (st + 1 < steps) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m) an[m] = load_a(At + ((st + 1) * ATILES + m) * 64 + lane);
+            fetch(st + 1, ya, yb);
+        }
+        const bool nin = 1 + 4 * st + lk <= h;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const float a_n = nin ? xa[t] + xb[t] : 0.f;
+            const float b_n = nin ? xa[t] - xb[t] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                Cm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m].x, a_n, Cm[t][m], 0, 0, 0);
+                Dm[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m].y, b_n, Dm[t][m], 0, 0, 0);
+            }
+        }
+        if (st + 1 < steps) {
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                xa[t] = ya[t];
+                xb[t] = yb[t];
+            }
+        }
+    }
+}
+
+// pfa_mfma for the split path's column tiles (no swizzle, run-time tile counts).
+template <int MT, int NTW, int ATILES = kMxTiles, class AP>
+__device__ __forceinline__ void pfa_mfma_cols(const float* bf, int s1, int p, int h, int mt, int ntw, AP At,
                                          float2 (&an)[MT], mf4 (&Cm)[NTW][MT], mf4 (&Dm)[NTW][MT]) {
     static_assert(MT <= ATILES, "A operand tiles");
     const int lane = (int)threadIdx.x & 63;
@@ -1181,7 +1278,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         load_trig<NT>(trig, h, glb(d->trig) + d->trig_off[j]);
     }
     __syncthreads();
-    fft_rows<NT, 64, 64>(buf, p, s1, lg, tw);
+    fft_rows<NT, 64, 64, MX>(buf, p, s1, lg, tw);
 
     // step B
     GLOBAL float2* __restrict__ E = glb(shifted ? io.E2 : io.E) + base;
@@ -1201,8 +1298,14 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         const float* bf = reinterpret_cast<const float*>(buf);
         const int mt = (h + 16) >> 4;
         const int ntw = s1 >> 6;
-        static_assert(MT == MTA, "first A operands");
-        pfa_mfma<MT, NTW>(bf, s1, p, h, mt, ntw, A, a0, Cm, Dm);
+        static_assert(MT == MTA && MT == kMxTiles && NTW == 2, "first A operands");
+        if (mt == 2) {
+            if (ntw == 2) pfa_mfma<2, 2>(bf, p, h, A, a0, Cm, Dm);
+            else pfa_mfma<2, 1>(bf, p, h, A, a0, Cm, Dm);
+        } else {
+            if (ntw == 2) pfa_mfma<1, 2>(bf, p, h, A, a0, Cm, Dm);
+            else pfa_mfma<1, 1>(bf, p, h, A, a0, Cm, Dm);
+        }
         const float sgn = plane ? -1.f : 1.f;
 #pragma unroll
         for (int q = 0; q < NK; ++q) hi[q] = 0;
@@ -1492,7 +1595,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
     mf4 Cm[1][MT], Dm[1][MT];
     const float* bf = reinterpret_cast<const float*>(tile);
     const int mt = (h + 16) >> 4;
-    pfa_mfma<MT, 1, kMxcTiles>(bf, C, p, h, mt, 1, A, a0, Cm, Dm);
+    pfa_mfma_cols<MT, 1, kMxcTiles>(bf, C, p, h, mt, 1, A, a0, Cm, Dm);
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int li = lane & 15;
