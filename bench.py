@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+MFMA_FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix cores
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n2e22_s64_batch256.txt")
 KERNELS_SRC = os.path.join(ROOT, "paper_1706_02740_amd", "csrc", "kernels.hip")
 
@@ -53,6 +54,10 @@ def kernel_work(info: dict) -> dict:
                and of the even/odd p-point step (8 s1 h^2, h = (p - 1) / 2, per DFT).
     Both sit below the FP32 ridge (about 9.8 flop/B without packed FP32), so
     their roofline is HBM bandwidth.
+    k_gather_mx: the same bytes and flops as k_gather, the band sums on the
+               matrix cores; it runs the wide windows (Theorem 4's preset: 45
+               taps, 40 bands at N = 2^22, about 21 flop/B), whose roofline is
+               the FP32 matrix-core peak.
     """
     Q, M, taps, s1 = info["Q"], info["M"], 2 * info["kappa"] + 1, info["s1"]
     gather_bytes = M * taps * 8 + Q * M * 8
@@ -60,8 +65,8 @@ def kernel_work(info: dict) -> dict:
     dft_bytes = Q * M * 8
     lg = int(math.log2(s1))
     dft_flops = Q * sum(5 * P * lg + 8 * s1 * ((p - 1) // 2) ** 2 for P, p in zip(info["P"], info["primes"]))
-    return {"k_gather": (gather_bytes, gather_flops, 0), "k_dft": (dft_bytes, dft_flops, Q * M * 8),
-            "k_dft_mx": (dft_bytes, dft_flops, Q * M * 8)}
+    return {"k_gather": (gather_bytes, gather_flops, 0), "k_gather_mx": (gather_bytes, gather_flops, 0),
+            "k_dft": (dft_bytes, dft_flops, Q * M * 8), "k_dft_mx": (dft_bytes, dft_flops, Q * M * 8)}
 
 
 def measured_traffic(kernel: str):
@@ -102,10 +107,17 @@ def roofline_of(dom: str, work: dict, kern: dict, tpl: dict, info: dict):
     if dom not in work or kern[dom]["avg_ms"] <= 0:
         return None
     byts, flops, extra = work[dom]
-    ach = byts * tpl[dom] / (kern[dom]["avg_ms"] * 1e-3) / 1e9
     tr = measured_traffic(dom)
     if tr and tr["transforms_per_launch"] != tpl[dom]:   # counters taken at another batch size
         tr = None
+    if dom == "k_gather_mx":   # band sums on the matrix cores: against their FP32 peak
+        ach = flops * tpl[dom] / (kern[dom]["avg_ms"] * 1e-3) / 1e12
+        return {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / MFMA_FP32_PEAK_TFLOPS, "traffic": tr["bytes"] if tr else None,
+                "traffic_detail": tr, "algorithmic_flops_per_launch": flops * tpl[dom],
+                "algorithmic_bytes_per_launch": byts * tpl[dom], "avg_launch_ms": kern[dom]["avg_ms"],
+                "transforms_per_launch": tpl[dom], "dispatches_per_launch": 1}
+    ach = byts * tpl[dom] / (kern[dom]["avg_ms"] * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None,
             "traffic_detail": tr,

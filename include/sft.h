@@ -88,6 +88,11 @@ extern "C" {
  * LDS, else 4 when it covers the plan, else 2 (sft_plan_info.dft_path reports
  * the choice).  Paths 1 and 2 give bitwise equal results, and so do paths 3
  * and 4; the matrix-core paths sum the p-point step in another order.
+ * gather_path chooses the filtered-sample kernel: 1 = band sums on the vector
+ * ALUs (one node per lane), 2 = band sums as a product on the matrix cores
+ * (s1 >= 16, up to 64 bands and 63 taps), 0 = automatic (2 when it covers the plan;
+ * sft_plan_info.gather_path reports the choice).  The two sum in different
+ * orders (results agree to FP32 rounding).
  * ident chooses the identification (SFT_IDENT_*).  SFT_IDENT_PHASE is the
  * phase-shift family that Section 5 pairs with CLW-DSFT (whose inner algorithm
  * the paper does not print): the filtered samples are also taken at every node
@@ -109,6 +114,7 @@ typedef struct sft_params {
     int32_t heavy_T;
     int32_t dft_path;
     int32_t ident;
+    int32_t gather_path;
 } sft_params;
 
 /*
@@ -146,6 +152,7 @@ typedef struct sft_plan_info {
     int32_t dft_split;  /* dft_path 3: the moduli [0, dft_split) run as a launch of their own with a
                            smaller LDS allocation per workgroup (more workgroups per CU); 0: one
                            launch (always 0 from sft_plan_describe) */
+    int32_t gather_path;  /* filtered-sample kernel the plan runs (1, 2; 0 from sft_plan_describe) */
 } sft_plan_info;
 
 typedef struct sft_plan_s* sft_plan_t;
@@ -327,7 +334,8 @@ SFT_API const char* sft_last_error(void);
 #define SFT_KERNEL_SELECT   6   /* split path: heavy-bin selection from global memory */
 #define SFT_KERNEL_DFT_MX   7   /* as SFT_KERNEL_DFT, the p-point step on the matrix cores */
 #define SFT_KERNEL_DFT_COLS_MX 8   /* as SFT_KERNEL_DFT_COLS, on the matrix cores */
-#define SFT_KERNEL_COUNT    9
+#define SFT_KERNEL_GATHER_MX 9   /* as SFT_KERNEL_GATHER, the band sums on the matrix cores */
+#define SFT_KERNEL_COUNT    10
 SFT_API int sft_profile_enable(int32_t on);
 SFT_API int sft_profile_reset(void);
 SFT_API int sft_profile_read(int32_t kernel, int64_t* launches, double* total_ms);

@@ -54,9 +54,11 @@ KERNEL_DFT_COLS = 5
 KERNEL_SELECT = 6
 KERNEL_DFT_MX = 7
 KERNEL_DFT_COLS_MX = 8
+KERNEL_GATHER_MX = 9
 KERNEL_NAMES = {KERNEL_GATHER: "k_gather", KERNEL_DFT: "k_dft", KERNEL_IDENTIFY: "k_identify",
                 KERNEL_MERGE: "k_merge", KERNEL_DFT_ROWS: "k_dft_rows", KERNEL_DFT_COLS: "k_dft_cols",
-                KERNEL_SELECT: "k_select", KERNEL_DFT_MX: "k_dft_mx", KERNEL_DFT_COLS_MX: "k_dft_cols_mx"}
+                KERNEL_SELECT: "k_select", KERNEL_DFT_MX: "k_dft_mx", KERNEL_DFT_COLS_MX: "k_dft_cols_mx",
+                KERNEL_GATHER_MX: "k_gather_mx"}
 
 MAX_MODULI = 15
 
@@ -81,7 +83,7 @@ class Params(ctypes.Structure):
     _fields_ = [("preset", ctypes.c_int32), ("kappa", ctypes.c_int32), ("sigma_t", ctypes.c_double),
                 ("tau", ctypes.c_double), ("r", ctypes.c_double), ("s1_mult", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("heavy_T", ctypes.c_int32), ("dft_path", ctypes.c_int32),
-                ("ident", ctypes.c_int32)]
+                ("ident", ctypes.c_int32), ("gather_path", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -93,7 +95,8 @@ class PlanInfo(ctypes.Structure):
                 ("c1", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("c2", ctypes.c_double), ("r", ctypes.c_double),
                 ("primes", ctypes.c_int32 * MAX_MODULI), ("dft_path", ctypes.c_int32),
-                ("P", ctypes.c_int64 * MAX_MODULI), ("M", ctypes.c_int64), ("dft_split", ctypes.c_int32)]
+                ("P", ctypes.c_int64 * MAX_MODULI), ("M", ctypes.c_int64), ("dft_split", ctypes.c_int32),
+                ("gather_path", ctypes.c_int32)]
 
 
 _lib = None
@@ -159,7 +162,7 @@ def require_device():
 
 
 def make_params(preset=PRESET_DMSFT6, kappa=0, sigma_t=0.0, tau=0.0, r=0.0, s1_mult=0,
-                group=0, heavy_T=0, dft_path=0, ident=IDENT_RESIDUE) -> Params:
+                group=0, heavy_T=0, dft_path=0, ident=IDENT_RESIDUE, gather_path=0) -> Params:
     if isinstance(preset, str):
         preset = PRESETS[preset]
     if isinstance(ident, str):
@@ -169,6 +172,7 @@ def make_params(preset=PRESET_DMSFT6, kappa=0, sigma_t=0.0, tau=0.0, r=0.0, s1_m
     p.kappa, p.sigma_t, p.tau, p.r = int(kappa), float(sigma_t), float(tau), float(r)
     p.s1_mult, p.group, p.heavy_T, p.dft_path = int(s1_mult), int(group), int(heavy_T), int(dft_path)
     p.ident = int(ident)
+    p.gather_path = int(gather_path)
     return p
 
 

@@ -158,14 +158,43 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     const bool valu_auto = fits && dft_lds_bytes(d) <= (size_t)lds_limit / 2;
     pl->split = path == 2 || path == 4 || (path == 0 && !mx_fits && !valu_auto);
     const bool cols_mx = pl->split && (path == 4 || (path == 0 && cmx_fits));
-    pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
+    // filtered samples: band sums on the matrix cores when the band table fits
+    // the kernel's tiles and its LDS, else on the vector ALUs
+    const int gpath = p ? p->gather_path : 0;
+    if (gpath < 0 || gpath > 2) {
+        delete pl;
+        return fail(SFT_EINVAL, "gather_path must be 0, 1 or 2");
+    }
+    d.gmx_mt = (2 * d.Q + 15) / 16;
+    d.gmx_ks = (2 * d.taps + 3) / 4;
+    // (tiles of 16 nodes lie within one modulus when 16 divides s1)
+    const bool gmx_fits = d.s1 >= 16 && d.gmx_mt <= kGmxMaxMT && d.gmx_ks <= kGmxMaxKS &&
+                          gather_mx_lds_bytes(d) <= lds_cap;
+    if (gpath == 2 && !gmx_fits) {
+        delete pl;
+        return fail(SFT_EUNSUPPORTED, "the matrix-core gather does not cover this plan (use gather_path 0 or 1)");
+    }
+    // automatic: the matrix cores for windows wider than 16 taps; narrower
+    // windows are faster on the vector ALUs (measured: N = 2^22, s = 64, 13
+    // taps, 0.60 vs 0.72 ms per 256 transforms; 45 taps, 11.4 vs 4.5 ms)
+    const bool use_gmx = gpath == 2 || (gpath == 0 && gmx_fits && d.taps > 16);
+    pl->info.gather_path = use_gmx ? 2 : 1;
+    if (use_gmx) {
+        // bits 32..39: M-tiles; bit 40: more than 16 taps (merged over a batch by maximum)
+        pl->lds[SFT_KERNEL_GATHER_MX] = gather_mx_lds_bytes(d) | ((size_t)d.gmx_mt << 32) |
+                                        ((size_t)(d.taps > 16) << 40);
+        pl->blocks[SFT_KERNEL_GATHER_MX] = gather_mx_blocks(d);
+    } else {
+        d.gmx_mt = d.gmx_ks = 0;
+        pl->lds[SFT_KERNEL_GATHER] = (size_t)d.taps;   // the gather launcher's tap count
+        pl->blocks[SFT_KERNEL_GATHER] = gather_blocks(d);
+    }
     d.vote_bitmap = identify_lds_bytes(d, true) <= lds_cap ? 1 : 0;
     // bit 32: the key vote; bit 33: phase identification (a batch takes each
     // when any of its plans needs it)
     pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d, d.vote_bitmap != 0) | ((size_t)(d.vote_bitmap == 0) << 32) |
                                    ((size_t)d.phase << 33);
     pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
-    pl->blocks[SFT_KERNEL_GATHER] = gather_blocks(d);
     pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);
     pl->blocks[SFT_KERNEL_MERGE] = merge_blocks(d);
     pl->info.dft_path = pl->split ? (cols_mx ? 4 : 2) : (path == 3 || (path == 0 && mx_fits)) ? 3 : 1;
@@ -301,10 +330,28 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
                     mxc[(((size_t)j * kMxcSteps + st) * kMxcTiles + m) * 64 + l] = v;
                 }
     }
+    // the matrix-core gather: the band table as the real matrix A (rows 2 b + e,
+    // columns 2 i + x) in lane order, and the window factors exp(-(i - kappa)^2 c)
+    const size_t n_gmxa = (size_t)d.gmx_mt * d.gmx_ks * 64, n_gmxg = (size_t)d.gmx_ks * 2;
+    std::vector<float> gmxa(n_gmxa, 0.f), gmxg(n_gmxg, 0.f);
+    for (int m = 0; m < d.gmx_mt; ++m)
+        for (int st = 0; st < d.gmx_ks; ++st)
+            for (int l = 0; l < 64; ++l) {
+                const int row = 16 * m + l % 16, col = 4 * st + l / 16;
+                const int b = row / 2, e = row % 2, i = col / 2, x = col % 2;
+                if (b >= d.Q || i >= taps) continue;
+                const float2 t = band[(size_t)b * taps + i];
+                gmxa[((size_t)m * d.gmx_ks + st) * 64 + l] = e == 0 ? (x == 0 ? t.x : -t.y) : (x == 0 ? t.y : t.x);
+            }
+    for (size_t i = 0; i < n_gmxg && (int)i < taps; ++i) {
+        const double o = (double)((int)i - d.kappa);
+        gmxg[i] = (float)exp(-o * o / (2.0 * info.sigma_t * info.sigma_t));
+    }
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al((size_t)Qpad * 4);
     const size_t b_trig = al(n_trig * 8), b_mxa = al(n_mxa * 8), b_mxc = al(n_mxc * 8);
-    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa + b_mxc;
+    const size_t b_gmxa = al(n_gmxa * 4), b_gmxg = al(n_gmxg * 4);
+    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa + b_mxc + b_gmxa + b_gmxg;
     hipError_t e = hipMalloc(&pl->tables, tbytes);
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(tables) failed"); }
     char* tb = static_cast<char*>(pl->tables);
@@ -315,6 +362,9 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     d.trig = reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate);
     d.mxa = reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate + b_trig);
     d.mxc = n_mxc ? reinterpret_cast<const float2*>(tb + b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa) : nullptr;
+    const size_t o_gmx = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa + b_mxc;
+    d.gmx_a = n_gmxa ? reinterpret_cast<const float*>(tb + o_gmx) : nullptr;
+    d.gmx_g = n_gmxg ? reinterpret_cast<const float*>(tb + o_gmx + b_gmxa) : nullptr;
     e = hipMemcpy(tb, band.data(), n_band * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band, tws1.data(), n_tws1 * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1, twp.data(), n_twp * 8, hipMemcpyHostToDevice);
@@ -326,6 +376,8 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     if (e == hipSuccess && n_mxc)
         e = hipMemcpy(tb + b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa, mxc.data(), n_mxc * 8,
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_gmxa) e = hipMemcpy(tb + o_gmx, gmxa.data(), n_gmxa * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_gmxg) e = hipMemcpy(tb + o_gmx + b_gmxa, gmxg.data(), n_gmxg * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(tables)"); }
     e = hipMalloc(&pl->ddesc, sizeof(SigDesc));
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(descriptor) failed"); }
@@ -428,12 +480,14 @@ hipError_t launch_gather_l(const BatchArgs& a, int b, size_t taps, hipStream_t s
 hipError_t launch_merge_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_merge(a, b, st); }
 
 // Launch order of the pipeline and the launcher of each kernel id.
-const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER,   SFT_KERNEL_DFT_MX,      SFT_KERNEL_DFT,
-                                      SFT_KERNEL_DFT_ROWS, SFT_KERNEL_DFT_COLS,    SFT_KERNEL_DFT_COLS_MX,
-                                      SFT_KERNEL_SELECT,   SFT_KERNEL_IDENTIFY,    SFT_KERNEL_MERGE};
+const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER,   SFT_KERNEL_GATHER_MX,   SFT_KERNEL_DFT_MX,
+                                      SFT_KERNEL_DFT,      SFT_KERNEL_DFT_ROWS,    SFT_KERNEL_DFT_COLS,
+                                      SFT_KERNEL_DFT_COLS_MX, SFT_KERNEL_SELECT,   SFT_KERNEL_IDENTIFY,
+                                      SFT_KERNEL_MERGE};
 const char* kNames[SFT_KERNEL_COUNT] = {"launch(gather)",   "launch(dft)",      "launch(identify)",
                                         "launch(merge)",    "launch(dft_rows)", "launch(dft_cols)",
-                                        "launch(select)",   "launch(dft_mx)",   "launch(dft_cols_mx)"};
+                                        "launch(select)",   "launch(dft_mx)",   "launch(dft_cols_mx)",
+                                        "launch(gather_mx)"};
 
 LaunchFn launcher(int k) {
     switch (k) {
@@ -445,6 +499,7 @@ LaunchFn launcher(int k) {
         case SFT_KERNEL_DFT_COLS: return launch_dft_cols;
         case SFT_KERNEL_DFT_MX: return launch_dft_mx;
         case SFT_KERNEL_DFT_COLS_MX: return launch_dft_cols_mx;
+        case SFT_KERNEL_GATHER_MX: return launch_gather_mx;
         default: return launch_select;
     }
 }
@@ -527,19 +582,25 @@ int batch_shape(const sft_plan_t* plans, int32_t count, const void* const* f_dev
         B.ws_total += p->wl.total;
         for (int k = 0; k < SFT_KERNEL_COUNT; ++k)
             if (k != SFT_KERNEL_GATHER) {   // field-wise maximum of (pairs << 32 | bytes); identify's flags: union;
-                                            // the selection's LDS-key bytes: 0 if any plan has 0
+                                            // the selection's LDS-key bytes: 0 if any plan has 0; the
+                                            // matrix-core gather: largest M-tile count, any wide window
                 if (p->blocks[k] == 0) continue;   // the plan does not use kernel k
                 const size_t ph = p->lds[k] >> 32, bh = B.lds[k] >> 32;
                 const size_t hi = k == SFT_KERNEL_IDENTIFY ? (ph | bh)
                                   : k == SFT_KERNEL_SELECT ? (!B.used[k] ? ph : (ph && bh ? std::max(ph, bh) : 0))
+                                  : k == SFT_KERNEL_GATHER_MX ? (std::max(ph & 0xff, bh & 0xff) | ((ph | bh) & 0x100))
                                                            : std::max(ph, bh);
                 B.used[k] = true;
                 const size_t lo = std::max(p->lds[k] & 0xffffffffu, B.lds[k] & 0xffffffffu);
                 B.lds[k] = (hi << 32) | lo;
             }
-        // one compile-time tap count when every transform shares it, else the generic kernel
-        if (i == 0) B.lds[SFT_KERNEL_GATHER] = p->lds[SFT_KERNEL_GATHER];
-        else if (B.lds[SFT_KERNEL_GATHER] != p->lds[SFT_KERNEL_GATHER]) B.lds[SFT_KERNEL_GATHER] = 0;
+        // one compile-time tap count when every transform of the vector-ALU
+        // gather shares it, else the generic kernel
+        if (p->blocks[SFT_KERNEL_GATHER] > 0) {
+            if (!B.used[SFT_KERNEL_GATHER]) B.lds[SFT_KERNEL_GATHER] = p->lds[SFT_KERNEL_GATHER];
+            else if (B.lds[SFT_KERNEL_GATHER] != p->lds[SFT_KERNEL_GATHER]) B.lds[SFT_KERNEL_GATHER] = 0;
+            B.used[SFT_KERNEL_GATHER] = true;
+        }
     }
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     B.m_desc = al(sizeof(void*) * count);

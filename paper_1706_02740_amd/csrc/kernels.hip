@@ -233,6 +233,8 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
 
 constexpr int kPhaseAnchor = 8;
 
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void store_bands(GLOBAL float2* __restrict__ S, int P, int b0, int nb, const float2* acc,
                                             float u, const CONSTANT float* rate, float step_rate) {
     float sn, cs;
@@ -436,6 +438,248 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
             }
             store_bands(S, P, b0, nb, acc, u, rate, step_rate);
         }
+        }
+    }
+}
+
+// --------------------------------------------------------- k_gather_mx ----
+// The same filtered samples with the band sums on the matrix cores.  One lane
+// per node, as in k_gather: node geometry, window, weights
+// W(u - o) = [wnorm exp(-u^2 c - 2 u c kappa) r^(o + kappa)] exp(-o^2 c),
+// r = exp(2 u c), c = inv2sig2 (the bracket by one exponential and a product
+// per tap, the last factor from the plan's gmx_g), y_i = f[(j' + i - kappa) mod N] W.
+// The band sums S'_b = sum_i y_i T[b][i] of the wave's 64 nodes are four real
+// products D = A B (tiles of 16 nodes): B[k][n] = y_{k/2}(node n) (k even:
+// real part, odd: imaginary part), A[2 b + e][k] the real form of T[b][k/2]
+// (e = 0: Re, 1: Im; gmx_a, in lane order), so that
+// D[2 b][n] + i D[2 b + 1][n] = S'_b(node n).  FP32 16x16x4 MFMAs: M = 16 rows
+// (8 bands), K = 4 (2 taps), N = 16 nodes.  A 4 x 4 transpose of (register,
+// 16-lane row) turns the lane-per-node values of a K-step into the operands of
+// the four tiles (lane l of tile t supplies B[4 st + l / 16][l % 16]), and the
+// same transpose of the accumulators returns every node's rows to its lane.
+// Then S_b = exp(2 pi i q_b u / N) S'_b, the phasor anchored every
+// kPhaseAnchor bands and rotated by exp(2 pi i u 2L / N) in between, as in
+// k_gather.  MTMAX M-tiles (8 bands each) are accumulated per pass over the
+// window.  TAPSMAX <= 16: the window in registers whole, loaded once; else
+// in chunks of 8 taps per pass, the next chunk's loads issued before the
+// current chunk's products.
+
+// 4 x 4 transpose of (register, row of 16 lanes): on return v[j] in row k
+// holds what v[k] held in row j (v_permlane32_swap, then v_permlane16_swap).
+__device__ __forceinline__ void transpose4(float (&v)[4]) {
+    const auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[0]), __float_as_uint(v[2]), false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[1]), __float_as_uint(v[3]), false, false);
+    const auto t01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+    const auto t23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+    v[0] = __uint_as_float(t01[0]);
+    v[1] = __uint_as_float(t01[1]);
+    v[2] = __uint_as_float(t23[0]);
+    v[3] = __uint_as_float(t23[1]);
+}
+
+template <int TAPSMAX, int MTMAX>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MTMAX > 2 ? 2 : 4))) k_gather_mx(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Where at = locate(a);
+    const CONSTANT SigDesc* d = desc_of(a, at.sig);
+    const IoDesc io = io_of(a, at.sig);
+    const int tid = (int)threadIdx.x;
+    if (at.blk == 0 && tid == 0) glb(io.status)[0] = 0;
+    const int lane = tid & 63;
+    const int M = d->M;
+    // every lane of a wave takes part in the transposes and products; lanes
+    // past the last node work on it again and store nothing (a wave wholly
+    // past it still takes part in the table's staging)
+    const int g0 = at.blk * kThreads + tid;
+    const bool mine = g0 < M;
+    const int g = mine ? g0 : M - 1;
+    const int K = d->K;
+    int j = 0;
+    while (j + 1 < K && g >= d->Moff[j + 1]) ++j;
+    const int l = g - d->Moff[j];
+    const int p = d->p[j];
+    const int P = d->P[j];
+    const int s1 = d->s1;
+    int n = (l & (s1 - 1)) * p + (l >> d->log2s1) * s1;   // node (n1 p + n2 s1) mod P
+    if (n >= P) n -= P;
+    const int64_t N = d->N;
+    const int64_t nN = (int64_t)n * N;
+    const int64_t num = 2 * nN + P, den = 2 * (int64_t)P;
+    int64_t jp = (int64_t)((double)num / (double)den);
+    const int64_t rem = num - jp * den;
+    if (rem < 0) --jp;
+    else if (rem >= den) ++jp;
+    const int32_t delta = (int32_t)(nN - jp * P);
+    const float u = (float)delta / (float)P;
+    const int kappa = d->kappa, taps = d->taps, Q = d->Q;
+    const GLOBAL float2* __restrict__ f = glb(io.f);
+    // window value i of the window starting at st0 (zero past the last tap)
+    auto tap = [&](int64_t st0, int i) -> float2 {
+        if (i >= taps) return make_float2(0.f, 0.f);
+        int64_t idx = st0 + i;
+        if (idx < 0) idx += N;
+        else if (idx >= N) idx -= N;
+        return ld2(f + idx);
+    };
+    // narrow windows (at most 16 taps), loaded whole before the table's staging:
+    // inside [0, N) as 16-byte pieces from the even index at or below the
+    // start, then shifted by the start's parity (as in k_gather)
+    const int64_t ab = (int64_t)(((uintptr_t)io.f >> 3) & 1);
+    auto load_window = [&](int64_t st0, float2 (&xw)[16]) {
+        const int64_t par = (st0 + ab) & 1;
+        if (st0 - par >= 0 && st0 + 18 <= N) {
+            const GLOBAL pod_f4* w4 = (const GLOBAL pod_f4*)(f + (st0 - par));
+            float2 cc[18];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                pod_f4 v = {0.f, 0.f, 0.f, 0.f};
+                if (2 * q <= taps) v = w4[q];   // the pieces that hold taps (uniform)
+                cc[2 * q] = make_float2(v.x, v.y);
+                cc[2 * q + 1] = make_float2(v.z, v.w);
+            }
+            const uint32_t mk = 0u - (uint32_t)par;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float2 lo = cc[i], hi = cc[i + 1];
+                const float2 v = make_float2(__uint_as_float((__float_as_uint(lo.x) & ~mk) | (__float_as_uint(hi.x) & mk)),
+                                             __uint_as_float((__float_as_uint(lo.y) & ~mk) | (__float_as_uint(hi.y) & mk)));
+                xw[i] = i < taps ? v : make_float2(0.f, 0.f);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) xw[i] = tap(st0, i);
+        }
+    };
+    float2 xw[TAPSMAX <= 16 ? 16 : 1];
+    float2 x0[TAPSMAX <= 16 ? 1 : 8];
+    if constexpr (TAPSMAX <= 16) load_window(jp - kappa, xw);
+    else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x0[q] = tap(jp - kappa, q);
+    }
+    const int MT = d->gmx_mt, KS = d->gmx_ks;
+    float* As = reinterpret_cast<float*>(smem);   // [MT][KS][64]
+    float* Gs = As + MT * KS * 64;                // [2 KS]
+    {
+        const int na = MT * KS * 64, ng = 2 * KS;
+        const GLOBAL float* ga = glb(d->gmx_a);
+        const GLOBAL float* gg = glb(d->gmx_g);
+        for (int i = tid; i < na; i += kThreads) As[i] = ga[i];
+        for (int i = tid; i < ng; i += kThreads) Gs[i] = gg[i];
+    }
+    __syncthreads();
+    if (g0 - lane >= M) return;   // the whole wave is past the last node
+    const float c = d->inv2sig2;
+    const float e_first = d->wnorm * expf(-u * u * c - 2.0f * u * c * (float)kappa);   // o = -kappa
+    const float r = expf(2.0f * u * c);
+    const CONSTANT float* rate = cst(d->rate);
+    float sn, cs;
+    sincospif(2.0f * u * d->a_step, &sn, &cs);
+    const float2 step = make_float2(cs, sn);
+    const size_t soff = (size_t)Q * d->Moff[j] + l;
+    const int nshift = d->phase;   // 0, or 1: also the node moved one grid step
+    for (int sh = 0; sh <= nshift; ++sh) {
+        const int64_t st0 = jp - kappa + sh;   // index of the window's first tap
+        if (sh > 0) {
+            if constexpr (TAPSMAX <= 16) load_window(st0, xw);
+            else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) x0[q] = tap(st0, q);
+            }
+        }
+        GLOBAL float2* __restrict__ S = glb(sh ? io.S2 : io.S) + soff;
+        // MTMAX M-tiles (8 bands each) per pass over the window
+        for (int m0 = 0; m0 < MT; m0 += MTMAX) {
+            mf4 acc[4][MTMAX];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int mm = 0; mm < MTMAX; ++mm) acc[t][mm] = mf4{0.f, 0.f, 0.f, 0.f};
+            float ew = e_first;
+            // K-steps c0 .. c0 + 3 (taps 2 c0 .. 2 c0 + 7) from their window values x
+            auto chunk = [&](int c0, const float2 (&x)[8]) {
+#pragma unroll
+                for (int u4 = 0; u4 < 4; ++u4) {
+                    const int st = c0 + u4;
+                    if (st >= KS) break;
+                    float b4[4];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float w = ew * Gs[2 * st + h];
+                        ew *= r;
+                        b4[2 * h] = x[2 * u4 + h].x * w;
+                        b4[2 * h + 1] = x[2 * u4 + h].y * w;
+                    }
+                    transpose4(b4);   // b4[t]: this lane's operand for tile t
+#pragma unroll
+                    for (int mm = 0; mm < MTMAX; ++mm) {
+                        if (m0 + mm >= MT) break;
+                        const float av = As[((m0 + mm) * KS + st) * 64 + lane];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[t][mm] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b4[t], acc[t][mm], 0, 0, 0);
+                    }
+                }
+            };
+            if constexpr (TAPSMAX <= 16) {
+#pragma unroll
+                for (int c0 = 0; c0 < 8; c0 += 4) {
+                    if (c0 >= KS) break;
+                    float2 x[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[q] = xw[2 * c0 + q];
+                    chunk(c0, x);
+                }
+            } else {
+                // a window inside [0, N) for the whole wave: fixed offsets from its first tap
+                const bool inner = __all(st0 >= 0 && st0 + 2 * KS <= N);
+                const GLOBAL float2* __restrict__ fw = f + st0;
+                auto tapw = [&](int i) -> float2 {
+                    if (!inner) return tap(st0, i);
+                    return i < taps ? ld2(fw + i) : make_float2(0.f, 0.f);
+                };
+                float2 x[8], nx[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) x[q] = m0 == 0 ? x0[q] : tapw(q);
+                for (int c0 = 0; c0 < KS; c0 += 4) {
+                    if (c0 + 4 < KS) {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) nx[q] = tapw(2 * (c0 + 4) + q);
+                    }
+                    chunk(c0, x);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[q] = nx[q];
+                }
+            }
+            // rows back to the node's lane: after the transposes o[jj][rr] is
+            // row 4 jj + rr of M-tile m, i.e. band 8 m + 2 jj + rr / 2, part rr % 2
+#pragma unroll
+            for (int mm = 0; mm < MTMAX; ++mm) {
+                const int m = m0 + mm;
+                if (m >= MT) break;
+                float o[4][4];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    float v4[4] = {acc[0][mm][rr], acc[1][mm][rr], acc[2][mm][rr], acc[3][mm][rr]};
+                    transpose4(v4);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) o[jj][rr] = v4[jj];
+                }
+                float2 ph = make_float2(1.f, 0.f);
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb) {   // band b = 8 m + bb, the phasor anchored at bb = 0
+                    const int b = 8 * m + bb;
+                    if (b >= Q) break;
+                    if (bb == 0) {
+                        sincospif(2.0f * u * rate[b], &sn, &cs);
+                        ph = make_float2(cs, sn);
+                    } else {
+                        ph = cmul(ph, step);
+                    }
+                    const float2 v = make_float2(o[bb >> 1][2 * (bb & 1)], o[bb >> 1][2 * (bb & 1) + 1]);
+                    if (mine) st2s(S + (size_t)b * P, cmul(v, ph));
+                }
+            }
         }
     }
 }
@@ -1023,7 +1267,6 @@ __device__ void emit_heavy_regs(const uint32_t (&hi)[NK], uint64_t valid, LoF lo
 
 static_assert(2 * kDftThreads <= kSelBins, "emit_heavy_regs offsets live in the histogram");
 
-typedef float mf4 __attribute__((ext_vector_type(4)));
 
 // The value held by lane l ^ 1 (DPP quad permutation 1, 0, 3, 2); every lane
 // of the wave must be active.
@@ -2486,6 +2729,8 @@ hipError_t configure_kernels(int max_lds) {
                          (const void*)k_identify<false, false, kThreads>, (const void*)k_identify<true, false, kThreads>,
                          (const void*)k_identify<false, true, kThreads>, (const void*)k_identify<true, true, kThreads>,
                          (const void*)k_identify<false, false, kIdentifyWide>,
+                         (const void*)k_gather_mx<16, 2>, (const void*)k_gather_mx<64, 6>,
+                         (const void*)k_gather_mx<64, 8>,
                          (const void*)k_merge, (const void*)k_dft_rows,
                          (const void*)k_dft_cols, (const void*)k_dft_cols_mx, (const void*)k_select<kThreads, false>,
                          (const void*)k_select<kSelLdsThreads, true>};
@@ -2530,6 +2775,23 @@ hipError_t launch_gather(const BatchArgs& a, int blocks, int taps, hipStream_t s
         case 13: hipLaunchKernelGGL(k_gather<13>, dim3(blocks), dim3(kThreads), 0, st, a); break;
         default: hipLaunchKernelGGL(k_gather<0>, dim3(blocks), dim3(kThreads), 0, st, a); break;
     }
+    return hipGetLastError();
+}
+
+int gather_mx_blocks(const SigDesc& d) { return (d.M + kThreads - 1) / kThreads; }
+
+size_t gather_mx_lds_bytes(const SigDesc& d) { return (size_t)d.gmx_mt * d.gmx_ks * 64 * 4 + (size_t)d.gmx_ks * 8; }
+
+hipError_t launch_gather_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
+    // bits 32..39: the largest M-tile count of the launch's plans; bit 40:
+    // some plan has more than 16 taps.  Wide windows: every M-tile in one pass
+    // over the window (up to 8; 6 when that covers the launch).
+    const size_t bytes = lds & 0xffffffffu;
+    const int mt = (int)((lds >> 32) & 0xff);
+    const dim3 gr(blocks), th(kThreads);
+    if (!((lds >> 40) & 1)) hipLaunchKernelGGL((k_gather_mx<16, 2>), gr, th, bytes, st, a);
+    else if (mt <= 6) hipLaunchKernelGGL((k_gather_mx<64, 6>), gr, th, bytes, st, a);
+    else hipLaunchKernelGGL((k_gather_mx<64, 8>), gr, th, bytes, st, a);
     return hipGetLastError();
 }
 

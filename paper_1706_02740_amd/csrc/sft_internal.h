@@ -29,6 +29,7 @@ constexpr int kMxcTiles = 3;           // h + 1 <= 48
 constexpr int kDftKBMax = 16;          // p-point output pairs per thread in the in-LDS short-DFT kernel
 constexpr int kSelLdsThreads = 1024;   // workgroup size of the split path's selection with its keys in LDS
 constexpr int kSelLdsMaxBlocks = 256;  // launches up to this many selection blocks (one per CU) take it
+constexpr int kGmxMaxMT = 8, kGmxMaxKS = 32;  // k_gather_mx: at most 64 bands and 63 taps
 
 // Status bits written by the device.
 constexpr int kStatusAcceptOverflow = 1;
@@ -85,6 +86,13 @@ struct SigDesc {
     // [K][kMxcSteps][kMxcTiles][64]: the same operands for the split path's
     // matrix-core column kernel (null when the plan does not use it)
     const float2* mxc;
+    // k_gather_mx: the band table as a real matrix, [gmx_mt][gmx_ks][64] in
+    // lane order (lane l of M-tile m, K-step st holds A[16 m + l % 16][4 st + l / 16],
+    // A[2 b + e][2 i + x]: e = 0: (Re T, -Im T), e = 1: (Im T, Re T) for x = 0, 1),
+    // and exp(-(i - kappa)^2 inv2sig2) for i < 2 gmx_ks (zero from taps on)
+    int32_t gmx_mt, gmx_ks;
+    const float* gmx_a;
+    const float* gmx_g;
 };
 
 // Per-transform pointers: input, outputs and workspace slices.
@@ -155,6 +163,11 @@ int identify_blocks(const SigDesc& d);
 int merge_blocks(const SigDesc& d);
 // taps: 2 kappa + 1 shared by every transform of the launch, or 0 (read per transform)
 hipError_t launch_gather(const BatchArgs& a, int blocks, int taps, hipStream_t st);
+// lds: the byte count (low 32 bits); above: the M-tile count (bits 32..39) and whether some
+// plan has more than 16 taps (bit 40), each the maximum over the launch's plans
+int gather_mx_blocks(const SigDesc& d);
+size_t gather_mx_lds_bytes(const SigDesc& d);
+hipError_t launch_gather_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_dft(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 // split short-DFT path for blocks larger than one workgroup's LDS

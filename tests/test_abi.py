@@ -59,7 +59,8 @@ def test_library_plan_equals_oracle_plan(N, s, kw):
     assert lib["q"] == orc.q
     assert lib["M"] == orc.M
     assert lib["depth"] == oracle.class_depth(orc.G)
-    assert lib["dft_path"] == 0 and lib["dft_split"] == 0   # device choices: set by sft_plan_create only
+    # device choices: set by sft_plan_create only
+    assert lib["dft_path"] == 0 and lib["dft_split"] == 0 and lib["gather_path"] == 0
     for name in ("sigma_t", "beta", "c1", "tau", "alpha", "c2", "r"):
         assert lib[name] == getattr(orc, name), name     # same FP64 formula, same order
 

@@ -44,6 +44,24 @@ def test_roofline_object_from_algorithmic_bytes():
     assert roof["overhead_bytes_per_launch"] == roof["algorithmic_bytes_per_launch"]
 
 
+def test_matrix_core_gather_roofline_is_the_fp32_mfma_peak():
+    """Theorem 4's preset at N = 2^22 (45 taps, Q = 40): the band sums are
+    8 flops per tap, band and node (a complex tap times a complex phasor,
+    accumulated), 0.628 GFLOP per transform; 256 transforms in 3.3 ms are
+    48.7 TFLOP/s, 0.31 of the FP32 matrix-core peak (157.3 TFLOP/s)."""
+    info = sft.describe(2 ** 22, 64, preset="theory")
+    assert info["kappa"] == 22 and info["Q"] == 40
+    work = bench.kernel_work(info)
+    assert work["k_gather_mx"] == work["k_gather"]
+    flops = work["k_gather_mx"][1]
+    assert flops == 40 * 43_648 * 45 * 8
+    kern = {"k_gather_mx": {"launches": 5, "total_ms": 5 * 3.3, "avg_ms": 3.3}}
+    roof = bench.roofline_of("k_gather_mx", work, kern, {"k_gather_mx": 256.0}, info)
+    assert roof["bound"] == "mfma" and roof["unit"] == "TFLOP/s" and roof["peak"] == 157.3
+    assert roof["achieved"] == pytest.approx(256 * flops / 3.3e-3 / 1e12)
+    assert 0.30 < roof["frac"] < 0.32
+
+
 def test_host_cpu_description():
     h = bench.host_cpu()
     assert h["nproc"] >= 1 and 1 <= h["usable_cpus"] <= h["nproc"]

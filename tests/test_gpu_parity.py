@@ -57,8 +57,11 @@ def assert_same_result(wg, cg, wo, co, tol=COEF_TOL):
     return rel
 
 
+LIBRARY_ONLY = ("dft_path", "gather_path")   # kernel choices: not plan parameters of the method
+
+
 def _oplan(N, s, kw):
-    return oracle.make_plan(N, s, oracle.Params(**{k: v for k, v in kw.items() if k != "dft_path"}))
+    return oracle.make_plan(N, s, oracle.Params(**{k: v for k, v in kw.items() if k not in LIBRARY_ONLY}))
 
 
 INTERMEDIATE_CASES = [
@@ -76,11 +79,19 @@ INTERMEDIATE_CASES = [
     ("auto_splitmx_n2e20_s100_30db", 2 ** 20, 100, 30.0, {}, 7),   # three row tiles (h = 41)
     # s1 = 256 with up to 13 output pairs per thread: the 33-slot VALU short DFT
     ("valu33_n2e18_s100_20db", 2 ** 18, 100, 20.0, {"dft_path": 1}, 8),
+    # the two gather kernels on the same inputs: band sums on the vector ALUs
+    # (gather_path 1) and on the matrix cores (2, the default where it applies;
+    # its A operands in registers for up to 16 bands and 16 taps, in LDS beyond)
+    ("gvalu_prime_n100003_s20_30db", 100_003, 20, 30.0, {"gather_path": 1}, 1),
+    ("gmx_prime_n100003_s20_30db", 100_003, 20, 30.0, {"gather_path": 2}, 1),
+    ("gvalu_n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2, "gather_path": 1}, 3),
+    ("gmx_n98304_s12_dmsft4", 3 * 2 ** 15, 12, 40.0, {"preset": 1, "gather_path": 2}, 2),
+    ("gmx_n64_s64", 64, 64, None, {"gather_path": 2}, 5),   # every window wraps
 ]
 
 
 def _okw(kw):
-    return {k: v for k, v in kw.items() if k != "dft_path"}
+    return {k: v for k, v in kw.items() if k not in LIBRARY_ONLY}
 
 
 def check_intermediates(gpu, plan, op, f32, bands=None):
@@ -209,16 +220,19 @@ def test_prime_n10000019_s128_40db(gpu):
 
 
 def test_batched_equals_plain_mixed_plans(gpu):
-    """One execute_many over transforms of different N, s and window widths
-    (13- and 9-tap plans together run the generic gather kernel) equals the
-    single-transform calls (which run the compile-time-tap kernels) bit for bit."""
-    shapes = [(2 ** 14, 8, 0), (100_003, 20, 0), (2 ** 16, 40, 1), (2 ** 14, 8, 0), (31, 1, 0),
-              (3 * 2 ** 15, 12, 1), (2 ** 14, 8, 2)]
+    """One execute_many over transforms of different N, s, window widths and
+    gather kernels (13- and 9-tap plans of the vector-ALU gather together run
+    its generic kernel; the matrix-core gather takes its LDS-operand form when
+    a plan needs it) equals the single-transform calls bit for bit."""
+    # (N, s, preset, gather_path): both gather kernels, and both forms of the
+    # matrix-core one (the theory preset's 31 taps need its LDS-operand form)
+    shapes = [(2 ** 14, 8, 0, 0), (100_003, 20, 0, 0), (2 ** 16, 40, 1, 0), (2 ** 14, 8, 0, 0), (31, 1, 0, 0),
+              (3 * 2 ** 15, 12, 1, 1), (2 ** 14, 8, 2, 0), (100_003, 20, 0, 1)]
     plans = {}
-    for N, s, pr in shapes:
-        if (N, s, pr) not in plans:
-            plans[(N, s, pr)] = gpu.Plan(N, s, preset=pr)
-    sigs = [siggen.sparse_signal(N, s, seed=50 + i, snr_db=30.0) for i, (N, s, _) in enumerate(shapes)]
+    for N, s, pr, gp in shapes:
+        if (N, s, pr, gp) not in plans:
+            plans[(N, s, pr, gp)] = gpu.Plan(N, s, preset=pr, gather_path=gp)
+    sigs = [siggen.sparse_signal(N, s, seed=50 + i, snr_db=30.0) for i, (N, s, _, _) in enumerate(shapes)]
     fs = [dev(sg.f32) for sg in sigs]
     pl = [plans[sh] for sh in shapes]
     say("batched mixed", len(shapes))
