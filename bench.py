@@ -331,9 +331,10 @@ def graph_replay(sft, torch, plans, inputs, steps: int, stream) -> dict:
 def tuning_sweep(sft, torch, batch: int = 64,
                  shapes=((2 ** 22, 16), (2 ** 22, 32), (2 ** 22, 64), (2 ** 22, 128), (2 ** 20, 100),
                          (2 ** 24, 128))) -> dict:
-    """The short-DFT path tuner on representative shapes (a fresh cache, so
-    every path is measured): ms per transform of each path the library
-    accepts, the tuner's choice, and the fixed rule's choice (dft_path 0)."""
+    """The kernel-configuration tuner on representative shapes (a fresh
+    cache, so every configuration is measured): ms per transform of each
+    configuration the library accepts, the tuner's choice, and the automatic
+    rule's choice (all fields 0)."""
     import tempfile
 
     from paper_1706_02740_amd import tune
@@ -341,11 +342,13 @@ def tuning_sweep(sft, torch, batch: int = 64,
     with tempfile.TemporaryDirectory() as tmp:
         cache = tune.Cache(os.path.join(tmp, "tune.json"))
         for N, s in shapes:
-            path = tune.best_dft_path(N, s, batch=batch, cache=cache)
+            cfg = tune.best_config(N, s, batch=batch, cache=cache)
             entry = next(v for k, v in cache.data.items() if f"N={N}|s={s}|" in k)
-            rule = sft.Plan(N, s).info["dft_path"]   # the automatic choice
-            out[f"N={N},s={s}"] = {"tuned": path, "rule": rule, "ms_per_transform": entry["ms_per_transform"]}
-    print("[bench] tuning: " + "; ".join(f"{k}: {v['tuned']} {v['ms_per_transform']}" for k, v in out.items()),
+            info = sft.Plan(N, s).info   # the automatic choice
+            rule = {"dft_path": info["dft_path"], "gather_path": info["gather_path"],
+                    "dft_split": info["dft_split"] if info["dft_split"] else -1}
+            out[f"N={N},s={s}"] = {"tuned": cfg, "rule": rule, "ms_per_transform": entry["ms_per_transform"]}
+    print("[bench] tuning: " + "; ".join(f"{k}: {tune.config_name(v['tuned'])}" for k, v in out.items()),
           file=sys.stderr, flush=True)
     return {"batch": batch, "shapes": out}
 

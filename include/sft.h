@@ -93,6 +93,10 @@ extern "C" {
  * (s1 >= 16, up to 64 bands and 63 taps), 0 = automatic (2 when it covers the plan;
  * sft_plan_info.gather_path reports the choice).  The two sum in different
  * orders (results agree to FP32 rounding).
+ * dft_split (dft_path 3 only): 0 = automatic (the moduli whose blocks fit
+ * three workgroups per CU run as a launch of their own when the largest do
+ * not), -1 = one launch, j >= 1 = the moduli [0, j) in a launch of their own
+ * (j < K); every choice gives the same results.
  * ident chooses the identification (SFT_IDENT_*).  SFT_IDENT_PHASE is the
  * phase-shift family that Section 5 pairs with CLW-DSFT (whose inner algorithm
  * the paper does not print): the filtered samples are also taken at every node
@@ -115,6 +119,7 @@ typedef struct sft_params {
     int32_t dft_path;
     int32_t ident;
     int32_t gather_path;
+    int32_t dft_split;
 } sft_params;
 
 /*

@@ -83,7 +83,7 @@ class Params(ctypes.Structure):
     _fields_ = [("preset", ctypes.c_int32), ("kappa", ctypes.c_int32), ("sigma_t", ctypes.c_double),
                 ("tau", ctypes.c_double), ("r", ctypes.c_double), ("s1_mult", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("heavy_T", ctypes.c_int32), ("dft_path", ctypes.c_int32),
-                ("ident", ctypes.c_int32), ("gather_path", ctypes.c_int32)]
+                ("ident", ctypes.c_int32), ("gather_path", ctypes.c_int32), ("dft_split", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -162,7 +162,7 @@ def require_device():
 
 
 def make_params(preset=PRESET_DMSFT6, kappa=0, sigma_t=0.0, tau=0.0, r=0.0, s1_mult=0,
-                group=0, heavy_T=0, dft_path=0, ident=IDENT_RESIDUE, gather_path=0) -> Params:
+                group=0, heavy_T=0, dft_path=0, ident=IDENT_RESIDUE, gather_path=0, dft_split=0) -> Params:
     if isinstance(preset, str):
         preset = PRESETS[preset]
     if isinstance(ident, str):
@@ -173,6 +173,7 @@ def make_params(preset=PRESET_DMSFT6, kappa=0, sigma_t=0.0, tau=0.0, r=0.0, s1_m
     p.s1_mult, p.group, p.heavy_T, p.dft_path = int(s1_mult), int(group), int(heavy_T), int(dft_path)
     p.ident = int(ident)
     p.gather_path = int(gather_path)
+    p.dft_split = int(dft_split)
     return p
 
 

@@ -137,6 +137,10 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
         delete pl;
         return fail(SFT_EINVAL, "dft_path must be 0, 1, 2, 3 or 4");
     }
+    if (p && (p->dft_split < -1 || p->dft_split >= d.K)) {
+        delete pl;
+        return fail(SFT_EINVAL, "dft_split must be -1, 0 or a modulus count below K");
+    }
     const bool fits = dft_fits_one_workgroup(d) && dft_lds_bytes(d) <= lds_cap;
     const int mx = dft_mfma_variant(d);
     const bool mx_fits = mx != 0 && dft_mx_lds_bytes(d, d.K) <= lds_cap;
@@ -209,9 +213,11 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
             // workgroups per CU take ~20 % less time per block than two).
             // The margin covers the static LDS and the allocation granularity.
             const size_t third = (size_t)lds_limit / 3 - 512;
-            if (pl->lds[SFT_KERNEL_DFT_MX] > third) {
-                int j1 = 0;
-                while (j1 < d.K && dft_mx_lds_bytes(d, j1 + 1) <= third) ++j1;
+            const int want = p ? p->dft_split : 0;   // 0: the rule above; -1: one launch; j: moduli [0, j)
+            if (want > 0 || (want == 0 && pl->lds[SFT_KERNEL_DFT_MX] > third)) {
+                int j1 = want;
+                if (want == 0)
+                    while (j1 < d.K && dft_mx_lds_bytes(d, j1 + 1) <= third) ++j1;
                 if (j1 > 0 && j1 < d.K) {
                     pl->mxs.min_blocks = 12 * cus;   // four rounds of three workgroups per CU
                     pl->mxs.j1 = j1;

@@ -1,21 +1,31 @@
-"""Autotuning of the short-DFT path per plan shape, with an on-disk cache.
+"""Autotuning of the kernel configuration per plan shape, with an on-disk cache.
 
-For a plan shape (N, s, parameters) and a batch size, every short-DFT path
-the library accepts for it (1: VALU in LDS, 2: split, 3: matrix cores in LDS,
-4: split with matrix-core columns; see sft_params.dft_path) is timed on a synthetic input with HIP events on the
-launch stream, and the fastest is kept.  All paths compute the same
-transform; paths 1 and 2 give bitwise equal results, as do paths 3 and 4,
-which sum the p-point step in another order.  Results are cached per device architecture, plan
-shape and batch-size class in a JSON file (``$SFT_TUNE_CACHE``, default
+A configuration is what the library lets a plan choose without changing the
+transform (sft_params): the short-DFT path (1: VALU in LDS, 2: split, 3:
+matrix cores in LDS, 4: split with matrix-core columns), the filtered-sample
+kernel (gather_path 1: one node per lane, band sums on the vector ALUs; 2:
+the band sums as matrix-core products) and, for path 3, the moduli split
+threshold (dft_split: -1 one launch, j the moduli [0, j) in a launch of their
+own with a smaller LDS allocation, 0 the library's LDS rule).  For a plan
+shape (N, s, parameters) and a batch size the tuner times, on a synthetic
+input with HIP events on the launch stream, every (dft_path, gather_path)
+pair the library accepts with the automatic split, then every split of the
+fastest pair when that pair runs path 3, and keeps the fastest.  All
+configurations compute the same transform (paths 1 and 2 bitwise equal, as
+are 3 and 4 and every split; the gathers and the two path families differ
+by rounding order).  Results are cached per device architecture, plan shape
+and batch-size class in a JSON file (``$SFT_TUNE_CACHE``, default
 ``~/.cache/paper_1706_02740_amd/tune.json``), so a shape is measured once.
 """
 from __future__ import annotations
 
 import json
 import os
-from typing import Callable, Dict, Optional
+from typing import Callable, Dict, Iterable, Optional
 
-PATHS = (3, 1, 4, 2)   # tried in this order; ties keep the earlier one
+PATHS = (3, 1, 4, 2)     # tried in this order; ties keep the earlier configuration
+GATHERS = (1, 2)
+TUNED = ("dft_path", "gather_path", "dft_split")
 
 
 def cache_path() -> str:
@@ -29,8 +39,12 @@ def batch_class(batch: int) -> str:
 
 
 def shape_key(arch: str, N: int, s: int, batch: int, params: dict) -> str:
-    p = {k: v for k, v in sorted(params.items()) if k != "dft_path"}
+    p = {k: v for k, v in sorted(params.items()) if k not in TUNED}
     return f"{arch}|N={int(N)}|s={int(s)}|{json.dumps(p, sort_keys=True)}|batch={batch_class(batch)}"
+
+
+def config_name(cfg: dict) -> str:
+    return f"dft{cfg['dft_path']}-gather{cfg['gather_path']}-split{cfg['dft_split']}"
 
 
 class Cache:
@@ -45,7 +59,8 @@ class Cache:
                 self.data = {}   # unreadable cache: measure again
 
     def get(self, key: str) -> Optional[dict]:
-        return self.data.get(key)
+        hit = self.data.get(key)
+        return hit if hit is not None and all(k in hit for k in TUNED) else None   # older entries: measure again
 
     def put(self, key: str, entry: dict) -> None:
         self.data[key] = entry
@@ -56,22 +71,38 @@ class Cache:
         os.replace(tmp, self.path)
 
 
-def choose(key: str, measure: Callable[[int], Optional[float]], cache: Cache) -> dict:
-    """The cached entry for key, else measure(path) -> ms per transform (None:
-    the library refuses the path for this shape) for every path, keep the
-    fastest and cache it."""
+def choose(key: str, measure: Callable[[dict], Optional[float]], cache: Cache,
+           splits: Callable[[dict], Iterable[int]] = lambda cfg: ()) -> dict:
+    """The cached entry for key, else: measure(config) -> ms per transform
+    (None: the library refuses the configuration) for every (dft_path,
+    gather_path) with the automatic split, then for the fastest, if it runs
+    path 3, every split in splits(config); keep the fastest and cache it."""
     hit = cache.get(key)
     if hit is not None:
         return hit
-    times = {}
+    times: Dict[str, float] = {}
+    order = []
     for path in PATHS:
-        ms = measure(path)
-        if ms is not None:
-            times[str(path)] = float(ms)
+        for g in GATHERS:
+            cfg = {"dft_path": path, "gather_path": g, "dft_split": 0}
+            ms = measure(cfg)
+            if ms is not None:
+                times[config_name(cfg)] = float(ms)
+                order.append(cfg)
     if not times:
-        raise RuntimeError(f"no short-DFT path accepts {key}")
-    best = min(times, key=lambda k: (times[k], PATHS.index(int(k))))
-    entry = {"dft_path": int(best), "ms_per_transform": times}
+        raise RuntimeError(f"no kernel configuration accepts {key}")
+    best = min(order, key=lambda c: (times[config_name(c)], order.index(c)))
+    if best["dft_path"] == 3:
+        for j in splits(best):
+            cfg = dict(best, dft_split=int(j))
+            if config_name(cfg) in times:
+                continue
+            ms = measure(cfg)
+            if ms is not None:
+                times[config_name(cfg)] = float(ms)
+                order.append(cfg)
+        best = min(order, key=lambda c: (times[config_name(c)], order.index(c)))
+    entry = dict(best, ms_per_transform=times)
     cache.put(key, entry)
     return entry
 
@@ -85,9 +116,9 @@ def _measure_on_device(N: int, s: int, batch: int, params: dict, reps: int = 3):
     f = torch.complex(torch.randn(N, device="cuda", generator=g),
                       torch.randn(N, device="cuda", generator=g)).to(torch.complex64)
 
-    def measure(path: int) -> Optional[float]:
+    def measure(cfg: dict) -> Optional[float]:
         try:
-            plan = Plan(N, s, dft_path=path, **params)
+            plan = Plan(N, s, **cfg, **params)
         except SftError as e:
             if e.code == SFT_EUNSUPPORTED:
                 return None
@@ -103,23 +134,37 @@ def _measure_on_device(N: int, s: int, batch: int, params: dict, reps: int = 3):
         b.synchronize()
         return a.elapsed_time(b) / (reps * batch)
 
-    return measure
+    def splits(cfg: dict):
+        K = Plan(N, s, **cfg, **params).info["K"]
+        return [-1] + list(range(1, K))
+
+    return measure, splits
+
+
+def _arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+
+
+def best_config(N: int, s: int, batch: int = 1, cache: Optional[Cache] = None, **params) -> dict:
+    """The fastest kernel configuration ({dft_path, gather_path, dft_split})
+    for transforms of this shape launched `batch` at a time on the current
+    device (measured once, then cached)."""
+    key = shape_key(_arch(), N, s, batch, params)
+    cache = cache or Cache()
+    hit = cache.get(key)
+    if hit is None:
+        measure, splits = _measure_on_device(N, s, batch, params)
+        hit = choose(key, measure, cache, splits)
+    return {k: hit[k] for k in TUNED}
 
 
 def best_dft_path(N: int, s: int, batch: int = 1, cache: Optional[Cache] = None, **params) -> int:
-    """The fastest short-DFT path for transforms of this shape launched
-    `batch` at a time on the current device (measured once, then cached)."""
-    import torch
-    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
-    key = shape_key(arch, N, s, batch, params)
-    cache = cache or Cache()
-    hit = cache.get(key)
-    if hit is not None:   # no device work at all
-        return hit["dft_path"]
-    return choose(key, _measure_on_device(N, s, batch, params), cache)["dft_path"]
+    """The short-DFT path of best_config."""
+    return best_config(N, s, batch, cache, **params)["dft_path"]
 
 
 def tuned_plan(N: int, s: int, batch: int = 1, cache: Optional[Cache] = None, **params):
-    """A Plan with the tuned short-DFT path."""
+    """A Plan with the tuned kernel configuration."""
     from . import Plan
-    return Plan(N, s, dft_path=best_dft_path(N, s, batch, cache, **params), **params)
+    return Plan(N, s, **best_config(N, s, batch, cache, **params), **params)

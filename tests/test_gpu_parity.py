@@ -57,7 +57,7 @@ def assert_same_result(wg, cg, wo, co, tol=COEF_TOL):
     return rel
 
 
-LIBRARY_ONLY = ("dft_path", "gather_path")   # kernel choices: not plan parameters of the method
+LIBRARY_ONLY = ("dft_path", "gather_path", "dft_split")   # kernel choices: not plan parameters of the method
 
 
 def _oplan(N, s, kw):
@@ -520,6 +520,32 @@ def test_matrix_core_moduli_split_rule(gpu):
     assert max(primes[:j1]) < min(primes[j1:]) and primes[j1 - 1] == 47
     assert gpu.Plan(2 ** 21, 32, dft_path=3).info["dft_split"] == 0
     assert gpu.Plan(2 ** 22, 64, dft_path=4).info["dft_split"] == 0
+
+
+def test_explicit_moduli_splits_are_bitwise_equal(gpu):
+    """dft_split (the tuner's third choice): one launch, the automatic split
+    and explicit thresholds give the same outputs bit for bit on a batch
+    large enough for the split to apply; an out-of-range value is refused."""
+    N, s = 2 ** 20, 32
+    fs = [dev(siggen.sparse_signal(N, s, seed=70 + i, snr_db=20.0).f32) for i in range(4)]
+    batch = [fs[i % 4] for i in range(128)]
+    ref = None
+    for split in (0, -1, 1, 3):
+        plan = gpu.Plan(N, s, dft_path=3, dft_split=split)
+        K = plan.info["K"]
+        assert plan.info["dft_split"] == (split if split > 0 else (0 if split == -1 else plan.info["dft_split"]))
+        say("dft_split", split, "->", plan.info["dft_split"], "K", K)
+        outs, counts = gpu.execute_many([plan] * len(batch), batch)
+        torch.cuda.synchronize()
+        got = [(o[0].cpu().numpy(), o[1].cpu().numpy()) for o in outs[:8]]
+        if ref is None:
+            ref = got
+        else:
+            for (w0, c0), (w1, c1) in zip(ref, got):
+                assert np.array_equal(w0, w1) and np.array_equal(c0, c1)
+    with pytest.raises(gpu.SftError) as ei:
+        gpu.Plan(N, s, dft_path=3, dft_split=K)
+    assert ei.value.code == gpu.SFT_EINVAL
 
 
 @pytest.mark.parametrize("snr", [0.0, -10.0])
