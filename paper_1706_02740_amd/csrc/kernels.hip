@@ -74,6 +74,7 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 typedef float pod_f4 __attribute__((ext_vector_type(4)));
+typedef int pod_i4 __attribute__((ext_vector_type(4)));
 
 // Copies n float2 (n even, both ends 16-byte aligned) from global memory into
 // LDS, 16 bytes per access, with U accesses of a thread in flight before its
@@ -2069,20 +2070,33 @@ __device__ __forceinline__ uint32_t fastmod_u32(uint32_t a, uint64_t magic, uint
 // largest |z| (ties to the smaller w), the band test w in [q_b - L, q_b + L),
 // and v = z / ghat_{w - q_b} in FP64.
 
-__device__ __forceinline__ float median_of(const float* v, int K) {
+// Median of v[0..K), K odd: the value whose rank (the values below it, and
+// the equal ones at a lower index) is K / 2.  Compiled for each K the plans
+// use (K = 2 G + 1), so that no comparison is guarded at run time.
+template <int KK>
+__device__ __forceinline__ float median_k(const float* v) {
     float med = 0.f;
 #pragma unroll
-    for (int i = 0; i < kMaxK; ++i) {
-        if (i < K) {
-            int rank = 0;
+    for (int i = 0; i < KK; ++i) {
+        int rank = 0;
 #pragma unroll
-            for (int k = 0; k < kMaxK; ++k) {
-                if (k < K) rank += (v[k] < v[i]) || (v[k] == v[i] && k < i);
-            }
-            if (rank == (K >> 1)) med = v[i];
-        }
+        for (int k = 0; k < KK; ++k) rank += (v[k] < v[i]) || (v[k] == v[i] && k < i);
+        if (rank == (KK >> 1)) med = v[i];
     }
     return med;
+}
+
+__device__ __forceinline__ float median_of(const float* v, int K) {
+    static_assert(kMaxK == 15, "median cases");
+    switch (K) {
+        case 5: return median_k<5>(v);
+        case 7: return median_k<7>(v);
+        case 9: return median_k<9>(v);
+        case 11: return median_k<11>(v);
+        case 13: return median_k<13>(v);
+        case 15: return median_k<15>(v);
+        default: return median_k<3>(v);   // K = 2 G + 1 >= 5; 3 for completeness
+    }
 }
 
 // Phase identification: bin h of a modulus of length P holds e (samples at the
@@ -2145,14 +2159,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOT
     int32_t* scratch = flag + acap;
     int32_t* pre = scratch + NT;
     uint8_t* ccount = reinterpret_cast<uint8_t*>(pre + ((nslots + 2) & ~1));   // [K * s1]
+    uint8_t* ccount2 = ccount + (((size_t)K * s1 + 3) & ~(size_t)3);            // [K * s1]: depth 8, second halves
     // heavy-bin bitmaps of the band's K blocks (when they fit the LDS): bit h of
     // block jj at word woff[jj] + h / 32; otherwise the vote compares keys
     constexpr bool use_bm = !KEYVOTE;
-    uint32_t* bm = reinterpret_cast<uint32_t*>(ccount + (((size_t)K * s1 + 3) & ~(size_t)3));
+    uint32_t* bm = reinterpret_cast<uint32_t*>(ccount2 + (((size_t)K * s1 + 3) & ~(size_t)3));
     int woff[kMaxK + 1];
     woff[0] = 0;
 #pragma unroll
     for (int jj = 0; jj < kMaxK; ++jj) woff[jj + 1] = woff[jj] + (jj < K && use_bm ? (d->P[jj] + 31) >> 5 : 0);
+    // slot of every combination (residue identification, at most kSlotMap of them)
+    uint16_t* cmap = reinterpret_cast<uint16_t*>(bm + woff[kMaxK]);
     __shared__ int32_t sh_cnt;
     __shared__ uint64_t sh_thr[kMaxK];   // the blocks' thresholds (key vote)
 
@@ -2168,48 +2185,114 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOT
     __syncthreads();   // bitmaps cleared
     {
         // class-list lengths (lists are -1 padded) and the heavy bins of block
-        // (jj, b) (its min(T, P_jj) entries of H, unordered); a thread's loads of
-        // a round are all issued before their first use
-        constexpr int U = 4;
+        // (jj, b) (its min(T, P_jj) entries of H, unordered), read as 16-byte
+        // pieces: a class list of depth 4 or 8 is one or two pieces, of depth
+        // 1 or 2 a piece holds 4 or 2 lists; a thread's loads are all issued
+        // before their first use
         const int nh = use_bm ? K * T : 0;
         const int ncl = phase ? 0 : K * s1;   // class lists: residue identification only
-        for (int i0 = tid; i0 < ncl || i0 < nh; i0 += U * NT) {
-            int32_t hv[U];
-            int32_t lv[U][kMaxDepth];
+        // the pieces' layout (uniform): T and s1 depth multiples of 4 (each
+        // block's lists and heavy bins then start at 16-byte boundaries)
+        const bool wide = (T & 3) == 0 && ((s1 * depth) & 3) == 0;
+        if (wide) {
+            constexpr int U = 4;
+            const int hq = T >> 2;                         // pieces of heavy bins per block
+            const int cq = (s1 * depth) >> 2;              // pieces of class lists per block
+            const int nhq = use_bm ? K * hq : 0, ncq = phase ? 0 : K * cq;
+            for (int i0 = tid; i0 < ncq || i0 < nhq; i0 += U * NT) {
+                pod_i4 hv[U], lv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * NT;
-                hv[u] = -1;
-                if (i < nh) {
-                    const int jj = i / T;
-                    const int e = i - jj * T;
-                    if (e < d->P[jj]) hv[u] = Hall[(size_t)(jj * Q + b) * T + e];
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * NT;
+                    hv[u] = pod_i4{-1, -1, -1, -1};
+                    lv[u] = pod_i4{-1, -1, -1, -1};
+                    if (i < nhq) {
+                        const int jj = i / hq;
+                        hv[u] = *(const GLOBAL pod_i4*)(Hall + (size_t)(jj * Q + b) * T + 4 * (i - jj * hq));
+                    }
+                    if (i < ncq) {
+                        const int jj = i / cq;
+                        lv[u] = *(const GLOBAL pod_i4*)(CLall + (size_t)(jj * Q + b) * cl_stride + 4 * (i - jj * cq));
+                    }
                 }
 #pragma unroll
-                for (int e = 0; e < kMaxDepth; ++e) lv[u][e] = -1;
-                if (i < ncl) {
-                    const GLOBAL int32_t* cl =
-                        CLall + (size_t)((i >> lg) * Q + b) * cl_stride + (size_t)(i & (s1 - 1)) * depth;
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * NT;
+                    if (i < nhq) {
+                        const int jj = i / hq;
+                        const int hs[4] = {hv[u].x, hv[u].y, hv[u].z, hv[u].w};
 #pragma unroll
-                    for (int e = 0; e < kMaxDepth; ++e)
-                        if (e < depth) lv[u][e] = cl[e];
+                        for (int e = 0; e < 4; ++e)
+                            if (hs[e] >= 0) atomicOr(&bm[woff[jj] + (hs[e] >> 5)], 1u << (hs[e] & 31));
+                    }
+                    if (i < ncq) {
+                        // entries 4 i .. 4 i + 3 of the band's lists (block jj = i / cq)
+                        const int jj = i / cq;
+                        const int e0 = 4 * (i - jj * cq);   // entry index within the block
+                        const int ls[4] = {lv[u].x, lv[u].y, lv[u].z, lv[u].w};
+                        if (depth >= 4) {   // whole piece in class e0 / depth; depth 8: two pieces
+                            int n = 0;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) n += ls[e] >= 0 ? 1 : 0;
+                            const int cidx = (jj << lg) + e0 / depth;
+                            if (depth == 4 || (e0 & 7) == 0) ccount[cidx] = (uint8_t)n;   // (first half)
+                            else ccount2[cidx] = (uint8_t)n;                                // second half
+                        } else {            // 4 / depth classes per piece
+#pragma unroll
+                            for (int e = 0; e < 4; e += depth) {
+                                int n = 0;
+                                for (int k = 0; k < depth; ++k) n += ls[e + k] >= 0 ? 1 : 0;
+                                ccount[(jj << lg) + (e0 + e) / depth] = (uint8_t)n;
+                            }
+                        }
+                    }
                 }
             }
+        } else {
+            constexpr int U = 4;
+            for (int i0 = tid; i0 < ncl || i0 < nh; i0 += U * NT) {
+                int32_t hv[U];
+                int32_t lv[U][kMaxDepth];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * NT;
-                if (hv[u] >= 0) {
-                    const int jj = i / T;
-                    atomicOr(&bm[woff[jj] + (hv[u] >> 5)], 1u << (hv[u] & 31));
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * NT;
+                    hv[u] = -1;
+                    if (i < nh) {
+                        const int jj = i / T;
+                        const int e = i - jj * T;
+                        if (e < d->P[jj]) hv[u] = Hall[(size_t)(jj * Q + b) * T + e];
+                    }
+#pragma unroll
+                    for (int e = 0; e < kMaxDepth; ++e) lv[u][e] = -1;
+                    if (i < ncl) {
+                        const GLOBAL int32_t* cl =
+                            CLall + (size_t)((i >> lg) * Q + b) * cl_stride + (size_t)(i & (s1 - 1)) * depth;
+#pragma unroll
+                        for (int e = 0; e < kMaxDepth; ++e)
+                            if (e < depth) lv[u][e] = cl[e];
+                    }
                 }
-                if (i < ncl) {
-                    int n = 0;
 #pragma unroll
-                    for (int e = 0; e < kMaxDepth; ++e) n += lv[u][e] >= 0 ? 1 : 0;
-                    ccount[i] = (uint8_t)n;
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * NT;
+                    if (hv[u] >= 0) {
+                        const int jj = i / T;
+                        atomicOr(&bm[woff[jj] + (hv[u] >> 5)], 1u << (hv[u] & 31));
+                    }
+                    if (i < ncl) {
+                        int n = 0;
+#pragma unroll
+                        for (int e = 0; e < kMaxDepth; ++e) n += lv[u][e] >= 0 ? 1 : 0;
+                        ccount[i] = (uint8_t)n;
+                    }
                 }
             }
         }
+    }
+    __syncthreads();
+    if (!phase && depth == 8 && ((T & 3) == 0) && ((s1 * depth) & 3) == 0) {
+        // depth 8 in pieces: a list's length is the sum of its halves' counts
+        for (int i = tid; i < K * s1; i += NT) ccount[i] = (uint8_t)(ccount[i] + ccount2[i]);
     }
     __syncthreads();
 
@@ -2227,6 +2310,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOT
     const int total = phase ? K * T : block_exclusive_scan<NT>(pre, nslots, scratch);
     if (tid == 0) pre[nslots] = total;
     __syncthreads();
+    const bool use_map = !phase && total <= kSlotMap;
+    if (use_map) {   // instead of a binary search over the slots per combination
+        for (int slot = tid; slot < nslots; slot += NT)
+            for (int i = pre[slot]; i < pre[slot + 1]; ++i) cmap[i] = (uint16_t)slot;
+        __syncthreads();
+    }
 
     // 2. candidates -> vote -> median
     const bool small_n = d->N <= ((int64_t)1 << 31);   // then B lies in the int32 range
@@ -2238,12 +2327,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOT
         int32_t hg[kMaxG];
     };
     auto prep = [&](int c, Combo& cb) {
-        int l0 = 0, h0 = nslots - 1;   // last slot with pre[slot] <= c
-        while (l0 < h0) {
-            const int mid = (l0 + h0 + 1) >> 1;
-            if (pre[mid] <= c) l0 = mid; else h0 = mid - 1;
+        int slot;
+        if (use_map) {
+            slot = cmap[c];
+        } else {
+            int l0 = 0, h0 = nslots - 1;   // last slot with pre[slot] <= c
+            while (l0 < h0) {
+                const int mid = (l0 + h0 + 1) >> 1;
+                if (pre[mid] <= c) l0 = mid; else h0 = mid - 1;
+            }
+            slot = l0;
         }
-        const int slot = l0;
         int r = c - pre[slot];
         cb.t = slot >> lg;
         cb.ac = slot & (s1 - 1);
@@ -2669,7 +2763,7 @@ size_t identify_lds_bytes(const SigDesc& d, bool bitmap) {
     if (bitmap)
         for (int j = 0; j < d.K; ++j) words += (size_t)(d.P[j] + 31) / 32;
     return (size_t)d.accept_cap * 20 + (size_t)kThreads * 4 + (size_t)((nslots + 2) & ~1) * 4 +
-           (((size_t)d.K * d.s1 + 3) & ~(size_t)3) + words * 4 + 64;
+           2 * (((size_t)d.K * d.s1 + 3) & ~(size_t)3) + words * 4 + (size_t)kSlotMap * 2 + 64;
 }
 
 size_t merge_lds_bytes() {

@@ -18,6 +18,7 @@ constexpr int kBandChunk = 16;         // bands accumulated per pass of the gene
 constexpr int kFastTaps = 16;          // window widths with a compile-time gather kernel are at most this
 constexpr int kAcceptCap = 4096;       // bound on the accepted candidates per band kept in LDS
 constexpr int kMergeCap = 4096;        // band results merged per signal in LDS
+constexpr int kSlotMap = 2048;         // k_identify: combinations whose (tuple, class) slot is tabulated in LDS
 constexpr int kRowElems = 4096;        // complex values per workgroup in the split path's row FFTs
 constexpr int kColChunk = 64;          // columns per workgroup in the split path's p-point DFTs
 constexpr int kMaxDepth = 8;           // class-list length bound (depth^G <= 64 with G >= 2)
