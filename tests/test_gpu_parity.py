@@ -144,6 +144,8 @@ def test_intermediates_match_oracle(gpu, name, N, s, snr, kw, seed):
     # Theorem 4's preset at the headline length: kappa = 22, the widest window (45 taps), Q = 40;
     # pins the uncompensated FP32 tap sums at 45 taps against the FP64 oracle
     ("theory_n2e22_s64_20db", 2 ** 22, 64, 20.0, {"preset": 2}, (0, 19, 39)),
+    # the same through the vector-ALU gather (tap by tap instead of 4-term matrix-core steps)
+    ("theory_valu_gather_n2e22_s64_20db", 2 ** 22, 64, 20.0, {"preset": 2, "gather_path": 1}, (0, 39)),
 ])
 def test_full_size_intermediates_match_oracle(gpu, name, N, s, snr, kw, bands):
     """Element-wise samples, bins and heavy sets at full-size plans, for three
