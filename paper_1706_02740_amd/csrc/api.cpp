@@ -64,7 +64,8 @@ static IoDesc carve(void* base, const WorkspaceLayout& wl) {
     io.Rw = reinterpret_cast<int64_t*>(p); p += wl.Rw;
     io.Rv = reinterpret_cast<double2*>(p); p += wl.Rv;
     io.Rn = reinterpret_cast<int32_t*>(p); p += wl.Rn;
-    io.status = reinterpret_cast<int32_t*>(p);
+    io.status = reinterpret_cast<int32_t*>(p); p += wl.status;
+    io.SH = wl.SH ? reinterpret_cast<int32_t*>(p) : nullptr;
     return io;
 }
 
@@ -392,6 +393,10 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
 
     // ---- the workspace of sft_execute is allocated by the plan's first sft_execute
     pl->wl = workspace_layout(info);
+    if (pl->blocks[SFT_KERNEL_DFT_COLS_MX]) {   // the column kernel's histograms for the selection
+        pl->wl.SH = ((size_t)d.K * d.Q * kSelBins * 4 + 255) & ~(size_t)255;
+        pl->wl.total += pl->wl.SH;
+    }
     pl->footprint = tbytes + sizeof(SigDesc);
     *out = pl;
     return SFT_OK;

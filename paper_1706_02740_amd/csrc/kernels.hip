@@ -1712,6 +1712,10 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     const int r0 = chunk * rows_per;
     const int rows = min(rows_per, p - r0);
     const size_t base = (size_t)d->Q * d->Moff[j] + (size_t)b * d->P[j] + ((size_t)r0 << lg);
+    if (io.SH && chunk == 0 && !shifted) {   // the block's top-digit histogram, filled by the column kernel
+        GLOBAL int32_t* sh = glb(io.SH) + (size_t)(j * d->Q + b) * kSelBins;
+        for (int i = tid; i < kSelBins; i += kThreads) sh[i] = 0;
+    }
     float2* buf = reinterpret_cast<float2*>(smem);
     float2* tw = buf + ((size_t)rows_per << lg);
     const int n = rows << lg;
@@ -1812,7 +1816,13 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
     const int P = d->P[j];
     const int h = (p - 1) >> 1;
     const size_t base = (size_t)Q * d->Moff[j] + (size_t)b * P;
-    float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]: the only LDS
+    float2* tile = reinterpret_cast<float2*>(smem);   // [p][C]
+    // the top key digit (bits 30..21 of |E|^2) of the tile's bins, added to the
+    // block's histogram for the selection (not for the shifted bins)
+    const bool hist_on = io.SH != nullptr && !shifted;
+    int32_t* hist = reinterpret_cast<int32_t*>(smem + (size_t)p * C * 8 + 64);   // [kSelBins], past the tile
+    if (hist_on)
+        for (int i = tid; i < kSelBins; i += kDftThreads) hist[i] = 0;   // ordered by the barrier below
     GLOBAL float2* __restrict__ E = glb(shifted ? io.E2 : io.E) + base;
     // the A operands [kMxcSteps][kMxcTiles][64] come from the plan's table
     // (L2-resident), one K-step ahead, as in k_dft
@@ -1867,7 +1877,17 @@ __global__ void __launch_bounds__(kDftThreads) k_dft_cols_mx(BatchArgs a) {
             if (k <= h && (plane == 0 || k >= 1)) {
                 const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
                 st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));   // two waves per line: plain
+                if (hist_on)
+                    atomicAdd(&hist[(__float_as_uint(fmaf(re, re, im * im)) >> (31 - kSelBits)) & (kSelBins - 1)], 1);
             }
+        }
+    }
+    if (hist_on) {
+        __syncthreads();
+        int32_t* sh = io.SH + (size_t)(j * Q + b) * kSelBins;
+        for (int i = tid; i < kSelBins; i += kDftThreads) {
+            const int v = hist[i];
+            if (v) atomicAdd(sh + i, v);
         }
     }
 }
@@ -1941,18 +1961,23 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
         }
         const bool all = d->T >= P;
         if (!all) {
-            for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
-            __syncthreads();
-            for (int base = 0; base < P; base += U * NT) {
-                float2 ev[U];
+            if (io.SH) {   // the histogram the column kernel formed with the bins
+                const GLOBAL int32_t* sh = glb(io.SH) + blk * kSelBins;
+                for (int i = tid; i < kSelBins; i += NT) hist[i] = sh[i];
+            } else {
+                for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
+                __syncthreads();
+                for (int base = 0; base < P; base += U * NT) {
+                    float2 ev[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int i = base + u * NT + tid;
-                    ev[u] = i < P ? ld2(E + i) : make_float2(0.f, 0.f);
+                    for (int u = 0; u < U; ++u) {
+                        const int i = base + u * NT + tid;
+                        ev[u] = i < P ? ld2(E + i) : make_float2(0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (base + u * NT + tid < P) atomicAdd(&hist[(hi_of(ev[u]) >> 21) & (kSelBins - 1)], 1);
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (base + u * NT + tid < P) atomicAdd(&hist[hi_of(ev[u]) >> 21], 1);
             }
             __syncthreads();
             // the bucket holding rank T, scanning the buckets in descending order
@@ -1988,7 +2013,7 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
             for (int u = 0; u < U; ++u) {
                 const int i = base + u * NT + tid;
                 const uint32_t h = hi_of(ev[u]);
-                const bool take = i < P && (h >> 21) >= dig;
+                const bool take = i < P && ((h >> 21) & (kSelBins - 1)) >= dig;
                 const uint64_t m = __ballot(take);
                 int wb = 0;
                 if (lane == 0 && m) wb = atomicAdd(&sh_nc, __popcll(m));
@@ -2791,7 +2816,7 @@ bool cols_mx_covers(const SigDesc& d) {
 size_t cols_mx_lds_bytes(const SigDesc& d) {
     int pmax = 0;
     for (int j = 0; j < d.K; ++j) pmax = std::max(pmax, d.p[j]);
-    return (size_t)pmax * 64 * 8 + 64;
+    return (size_t)pmax * 64 * 8 + 64 + (size_t)kSelBins * 4;   // the tile, then the selection's histogram
 }
 int select_blocks(const SigDesc& d) { return d.K * d.Q; }
 

@@ -232,7 +232,8 @@ WorkspaceLayout workspace_layout(const sft_plan_info& in) {
     w.Rv = align256((size_t)in.Q * in.s * 16);
     w.Rn = align256((size_t)in.Q * 4);
     w.status = 256;
-    w.total = w.S + w.E + w.S2 + w.E2 + w.H + w.thr + w.CL + w.Rw + w.Rv + w.Rn + w.status;
+    w.SH = 0;   // set by sft_plan_create for plans whose column kernel fills the selection's histograms
+    w.total = w.S + w.E + w.S2 + w.E2 + w.H + w.thr + w.CL + w.Rw + w.Rv + w.Rn + w.status + w.SH;
     return w;
 }
 

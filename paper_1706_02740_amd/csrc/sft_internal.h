@@ -113,6 +113,8 @@ struct IoDesc {
     double2* Rv;      // [Q*s] band results: coefficients
     int32_t* Rn;      // [Q] band result counts
     int32_t* status;  // [1]
+    int32_t* SH;      // [K*Q*kSelBins] split path with matrix-core columns: per block, the histogram of
+                      // the bins' top key digit (filled by the column kernel), else null
 };
 
 // Kernel launch argument: one transform (io_many == nullptr), a batch of one
@@ -141,7 +143,7 @@ struct MxSplit {
 
 // Per-signal workspace sizes in bytes (each slice 256-byte aligned).
 struct WorkspaceLayout {
-    size_t S, E, S2, E2, H, thr, CL, Rw, Rv, Rn, status, total;
+    size_t S, E, S2, E2, H, thr, CL, Rw, Rv, Rn, status, SH, total;
 };
 
 // plan.cpp
