@@ -1275,6 +1275,21 @@ __device__ __forceinline__ float lane_pair(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 
+// The value held by lane l ^ 8 within each row of 16 lanes (DPP row rotation
+// by 8); every lane of the wave must be active.
+__device__ __forceinline__ float lane_half(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));
+}
+
+// Column layout of k_dft's matrix-core step: wave w owns the N-tiles of the
+// 16 complex columns 16 w .. 16 w + 15 (tiles 2 w and 2 w + 1, s1 = 128) or
+// the 8 columns 8 w .. 8 w + 7 (s1 = 64), and lane l of an N-tile reads the
+// real part (l % 16 < 8) or the imaginary part (l % 16 >= 8) of the tile's
+// column l % 8, so that after the combine lanes 0-7 of a row hold X_k and
+// lanes 8-15 X_{p-k} of eight consecutive columns.
+__device__ __forceinline__ int mx_tile(int w, int t, int ntw) { return ntw == 2 ? 2 * w + t : w; }
+__device__ __forceinline__ int mx_fcol(int li) { return ((li & 7) << 1) | (li >> 3); }
+
 // Step B on the matrix cores.  Real form of the p-point step: N = 2 c + part
 // indexes the real (part 0) and imaginary (part 1) planes of the [p][s1]
 // block, a_n = x_n + x_{p-n}, b_n = x_n - x_{p-n}, and for k = 0..h
@@ -1284,7 +1299,8 @@ __device__ __forceinline__ float lane_pair(float v) {
 // FP32 16x16x4 MFMAs: M = 16 values of k, N = 16 floats (8 columns), K = 4
 // values of n.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
 // receives D[4 (l / 16) + r][l % 16] in register r.  Wave w owns the N-tiles
-// w + 8 t, t < NTW = s1 / 64, and the M-tiles m < MT = ceil((h + 1) / 16).
+// mx_tile(w, t), t < NTW = s1 / 64 (lane l reading float mx_fcol(l % 16) of
+// the tile), and the M-tiles m < MT = ceil((h + 1) / 16).
 // bf: the block as floats, columns swizzled by swz_col.  At: the A operands in
 // lane order ((st ATILES + m) 64 + lane, as the plan's mxa and mxc tables), in
 // LDS or global memory; an: on entry the operands of step 0
@@ -1314,7 +1330,7 @@ __device__ __forceinline__ void pfa_mfma(const float* bf, int p, int h, AP At, f
     const int steps = (h + 3) >> 2;   // <= kMxSteps
     int col[NTW];                     // the lane's float column in each N-tile
 #pragma unroll
-    for (int t = 0; t < NTW; ++t) col[t] = 16 * (wid + 8 * t) + li;
+    for (int t = 0; t < NTW; ++t) col[t] = 16 * mx_tile(wid, t, NTW) + mx_fcol(li);
     auto at = [&](int row, int t) { return row * RS + (col[t] ^ (2 * swz_col(row))); };
     const int ra = 1 + lk, rb = p - 1 - lk;   // the lane's rows n and p - n at step 0
     int oa[NTW], ob[NTW];
@@ -1431,11 +1447,12 @@ struct ValuClassThreads {
     int count, lg;
     __device__ int operator()(int c, int i) const { return (i << lg) + c; }
 };
-// Threads of the MFMA step B holding residue class c: N-tile c / 8 (wave
-// (c / 8) mod 8), lanes 16 lk + 2 (c mod 8) + part.
+// Threads of the MFMA step B holding residue class c (column c): the wave
+// of its N-tile (mx_tile), lanes 16 lk + 8 part + c mod 8.
 struct MfmaClassThreads {
     int count;   // 8
-    __device__ int operator()(int c, int i) const { return 64 * ((c >> 3) & 7) + 16 * (i >> 1) + 2 * (c & 7) + (i & 1); }
+    int sh;      // wave of column c: c >> sh (4: s1 = 128, 3: s1 = 64)
+    __device__ int operator()(int c, int i) const { return 64 * (c >> sh) + 16 * (i >> 1) + 8 * (i & 1) + (c & 7); }
 };
 
 // One workgroup per (modulus j, band b); the whole block in LDS.
@@ -1447,9 +1464,10 @@ struct MfmaClassThreads {
 // k0 + kk and p - k0 - kk; slot 2 KBMAX: row 0, group 0 only).
 // MX: step B on the matrix cores (pfa_mfma, up to MT = NTW = 2).  Requires
 // s1 = 64 or 128 and h + 1 <= 32 for every modulus.  Slot (t MT + m) 4 + r
-// holds the key of row k = 16 m + 4 r + l / 16 of N-tile w + 8 t: X_k in
-// even lanes, X_{p-k} in odd lanes (row 0 in even lanes only); the rows of a
-// register are consecutive, so registers whose rows all exceed h are skipped.  LDS: the block
+// holds the key of row k = 16 m + 4 r + l / 16 of N-tile mx_tile(w, t): X_k
+// in lanes l % 16 < 8, X_{p-k} in the others (row 0 in the first only); the
+// rows of a register are consecutive, so registers whose rows all exceed h
+// are skipped.  The bins go to E as whole 128-byte lines (s1 = 128).  LDS: the block
 // and the s1 twiddles only (the A operands come from the plan's table in
 // global memory); the selection's scratch reuses the block's space, so a
 // launch over the smaller moduli (BatchArgs::jn) needs less LDS per
@@ -1536,7 +1554,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     const int wid = tid >> 6;
     const int li = lane & 15;
     const int lk = lane >> 4;
-    const int plane = li & 1;   // 0: real, 1: imaginary plane (MFMA step B)
+    const int plane = li >> 3;   // MFMA step B: 0 real plane / X_k, 1 imaginary plane / X_{p-k}
     if constexpr (MT > 0) {
         mf4 Cm[NTW][MT], Dm[NTW][MT];
         const float* bf = reinterpret_cast<const float*>(buf);
@@ -1553,38 +1571,44 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         const float sgn = plane ? -1.f : 1.f;
 #pragma unroll
         for (int q = 0; q < NK; ++q) hi[q] = 0;
+        float x0v[NTW];
 #pragma unroll
-        for (int t = 0; t < NTW; ++t) {
-            if (t >= ntw) break;
-            const int N = 16 * (wid + 8 * t) + li;
-            const int c = N >> 1;
-            const float x0v = bf[N];
+        for (int t = 0; t < NTW; ++t) x0v[t] = t < ntw ? bf[16 * mx_tile(wid, t, ntw) + mx_fcol(li)] : 0.f;
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                if (m >= mt) break;
+        for (int m = 0; m < MT; ++m) {
+            if (m >= mt) break;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (16 * m + 4 * r > h) break;   // rows 16 m + 4 r .. + 3: all padding (uniform)
+            for (int r = 0; r < 4; ++r) {
+                if (16 * m + 4 * r > h) break;   // rows 16 m + 4 r .. + 3: all padding (uniform)
+                const int k = 16 * m + 4 * r + lk;
+                float2 x[NTW];
+#pragma unroll
+                for (int t = 0; t < NTW; ++t) {
+                    if (t >= ntw) break;
                     const int q = (t * MT + m) * 4 + r;
-                    const int k = 16 * m + 4 * r + lk;
                     const float cv = Cm[t][m][r];
-                    const float dp = lane_pair(Dm[t][m][r]);
-                    const float xk = (x0v + cv + sgn * dp) * scale;
-                    const float xm = (x0v + cv - sgn * dp) * scale;
-                    const float xk2 = lane_pair(xk);
-                    const float xm2 = lane_pair(xm);
-                    // even lanes key X_k = (xk, xk2), odd lanes X_{p-k} = (xm2, xm)
-                    const float re = plane ? xm2 : xk;
-                    const float im = plane ? xm : xk2;
-                    hi[q] = __float_as_uint(fmaf(re, re, im * im));
-                    // even lanes store X_k, odd lanes X_{p-k} (X_0 once, by the even lane)
-                    if (k <= h && (plane == 0 || k >= 1)) {
-                        const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
-                        // plain store: two waves fill each 128-byte line of E here, which
-                        // the L2 combines (a streaming store writes the halves separately)
-                        st2(E + (row << lg) + (uint32_t)c, make_float2(re, im));
-                        valid |= (uint64_t)1 << q;
-                    }
+                    const float dp = lane_half(Dm[t][m][r]);
+                    const float xk = (x0v[t] + cv + sgn * dp) * scale;
+                    const float xm = (x0v[t] + cv - sgn * dp) * scale;
+                    const float xk2 = lane_half(xk);
+                    const float xm2 = lane_half(xm);
+                    // lanes 0-7 hold X_k = (xk, xk2), lanes 8-15 X_{p-k} = (xm2, xm)
+                    x[t] = make_float2(plane ? xm2 : xk, plane ? xm : xk2);
+                    hi[q] = __float_as_uint(fmaf(x[t].x, x[t].x, x[t].y * x[t].y));
+                    if (k <= h && (plane == 0 || k >= 1)) valid |= (uint64_t)1 << q;   // X_0 once
+                }
+                if (ntw == 2) {
+                    // rows k and p - k of the wave's 16 columns, one full 128-byte line per
+                    // 16 lanes: lanes 0-7 of tile 2w with lanes 0-7 of tile 2w + 1 (row k),
+                    // lanes 8-15 of both (row p - k); streamed, as the lines are whole
+                    const float2 y0 = make_float2(lane_half(x[0].x), lane_half(x[0].y));
+                    const float2 y1 = make_float2(lane_half(x[1].x), lane_half(x[1].y));
+                    const uint32_t col = (uint32_t)(16 * wid + li);
+                    if (k <= h) st2s(E + ((uint32_t)k << lg) + col, plane ? y1 : x[0]);
+                    if (k >= 1 && k <= h) st2s(E + ((uint32_t)(p - k) << lg) + col, plane ? x[1] : y0);
+                } else if (k <= h && (plane == 0 || k >= 1)) {
+                    const uint32_t row = plane ? (uint32_t)(p - k) : (uint32_t)k;
+                    st2s(E + (row << lg) + (uint32_t)(8 * wid + (li & 7)), x[0]);
                 }
             }
         }
@@ -1626,8 +1650,8 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         if constexpr (MT > 0) {
             const int t = q / (MT * 4);
             const int k = 16 * ((q >> 2) % MT) + 4 * (q & 3) + ((th >> 4) & 3);
-            const int c = (16 * ((th >> 6) + 8 * t) + (th & 15)) >> 1;
-            return (((th & 1) ? p - k : k) << lg) + c;
+            const int c = 8 * mx_tile(th >> 6, t, s1 >> 6) + (th & 7);
+            return (((th >> 3) & 1 ? p - k : k) << lg) + c;
         } else {
             const int c = th & (s1 - 1);
             if (q == NK - 1) return c;
@@ -1672,7 +1696,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         emit_heavy_regs<NT, NK>(hi, valid, lo_of, ct, lg, d->T, d->depth, thr, hk, hist, part, cl,
                                 glb(io.H) + blk * d->T, glb(io.thr) + blk, glb(io.CL) + blk * (size_t)s1 * d->depth);
     };
-    if constexpr (MT > 0) emit(MfmaClassThreads{8});
+    if constexpr (MT > 0) emit(MfmaClassThreads{8, lg == 7 ? 4 : 3});
     else emit(ValuClassThreads{NT >> lg, lg});
 }
 
