@@ -1000,7 +1000,9 @@ static_assert(kSelBins == 1 << kSelBits, "bucket count");
 // each(f) calls f(hi, full) for every key k this thread holds, with hi = k >> 32
 // and full() returning k (which may cost more: it is called only in passes
 // whose digit reaches below bit 32, and only for keys whose hi matches).
-template <int NT, class EachKey>
+// FILLED: hist already holds the first digit's histogram of every key with
+// bit 63 clear (the caller formed it and passed a barrier since).
+template <int NT, bool FILLED = false, class EachKey>
 __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32_t* part) {
     __shared__ int32_t sh_digit, sh_need, sh_done;
     constexpr int BPT = kSelBins / NT;   // buckets per thread
@@ -1015,6 +1017,7 @@ __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32
         const int width = top < kSelBits ? top : kSelBits;
         const int shift = top - width;
         const uint64_t dmask = ((uint64_t)1 << width) - 1;
+        if (!FILLED || top != 63) {
         for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
         __syncthreads();
         const uint32_t pm_hi = (uint32_t)(pmask >> 32), pre_hi = (uint32_t)(prefix >> 32);
@@ -1033,6 +1036,7 @@ __device__ uint64_t kth_largest(EachKey each, int P, int T, int32_t* hist, int32
             });
         }
         __syncthreads();
+        }
         const int nb = 1 << width;
         int cnt[BPT];
         int loc = 0;
@@ -1508,8 +1512,10 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     float2* trig = tw + s1;   // VALU step B: the cosine/sine table [hmax^2]
     // selection scratch: after the table (VALU step B), or over the block
     // once step B has read it (MX)
-    int32_t* hist = MX ? reinterpret_cast<int32_t*>(smem) : reinterpret_cast<int32_t*>(trig + hmax * hmax);
-    int32_t* part = hist + kSelBins;
+    // MX: the first digit's histogram sits past the twiddles and is formed as
+    // the bins are; the rest of the scratch overlays the block
+    int32_t* hist = MX ? reinterpret_cast<int32_t*>(tw + s1) : reinterpret_cast<int32_t*>(trig + hmax * hmax);
+    int32_t* part = MX ? reinterpret_cast<int32_t*>(smem) : hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [T]
     int32_t* cl = reinterpret_cast<int32_t*>(hk + d->T);        // [s1 depth]
 
@@ -1530,6 +1536,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
             tw[tid] = w;
             tw[tid + (s1 >> 1)] = make_float2(-w.x, -w.y);
         }
+        for (int i = tid; i < kSelBins; i += NT) hist[i] = 0;
     } else {
         copy_to_lds<NT, 8>(buf, S, P);
         for (int i = tid; i < (s1 >> 1); i += NT) {   // the full circle: W^(m + s1/2) = -W^m
@@ -1595,7 +1602,10 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
                     // lanes 0-7 hold X_k = (xk, xk2), lanes 8-15 X_{p-k} = (xm2, xm)
                     x[t] = make_float2(plane ? xm2 : xk, plane ? xm : xk2);
                     hi[q] = __float_as_uint(fmaf(x[t].x, x[t].x, x[t].y * x[t].y));
-                    if (k <= h && (plane == 0 || k >= 1)) valid |= (uint64_t)1 << q;   // X_0 once
+                    if (k <= h && (plane == 0 || k >= 1)) {   // X_0 once
+                        valid |= (uint64_t)1 << q;
+                        if (!shifted && (int32_t)hi[q] >= 0) atomicAdd(&hist[hi[q] >> (31 - kSelBits)], 1);
+                    }
                 }
                 if (ntw == 2) {
                     // rows k and p - k of the wave's 16 columns, one full 128-byte line per
@@ -1690,7 +1700,7 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
             if ((valid >> q) & 1) f(hi[q], [&] { return ((uint64_t)hi[q] << 32) | lo_of(q, tid); });
         }
     };
-    const uint64_t thr = kth_largest<NT>(each, P, d->T, hist, part);
+    const uint64_t thr = kth_largest<NT, MX>(each, P, d->T, hist, part);
     const size_t blk = (size_t)(j * Q + b);
     auto emit = [&](auto ct) {
         emit_heavy_regs<NT, NK>(hi, valid, lo_of, ct, lg, d->T, d->depth, thr, hk, hist, part, cl,

@@ -251,12 +251,12 @@ size_t dft_lds_bytes(const SigDesc& d) {
 }
 
 size_t dft_mx_lds_bytes(const SigDesc& d, int jhi) {
-    // the block (8 B per bin) and the s1 twiddles; once step B has read the
-    // block, the selection's histogram, scan partials, T heavy keys and class
-    // lists take its place
+    // the block (8 B per bin), the s1 twiddles and the selection's first
+    // histogram; once step B has read the block, the scan partials, T heavy
+    // keys and class lists take its place
     const size_t block = (size_t)d.P[jhi - 1] * 8 + (size_t)d.s1 * 8;
-    const size_t scratch = (size_t)kSelBins * 4 + 64 + (size_t)d.T * 8 + (size_t)d.s1 * d.depth * 4;
-    return std::max(block, scratch) + 64;
+    const size_t scratch = 64 + (size_t)d.T * 8 + (size_t)d.s1 * d.depth * 4;
+    return std::max(block, scratch) + (size_t)kSelBins * 4 + 64;
 }
 
 int dft_pairs_per_thread(const SigDesc& d) {
