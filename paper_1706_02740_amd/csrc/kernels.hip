@@ -1512,9 +1512,11 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
     float2* trig = tw + s1;   // VALU step B: the cosine/sine table [hmax^2]
     // selection scratch: after the table (VALU step B), or over the block
     // once step B has read it (MX)
-    // MX: the first digit's histogram sits past the twiddles and is formed as
-    // the bins are; the rest of the scratch overlays the block
-    int32_t* hist = MX ? reinterpret_cast<int32_t*>(tw + s1) : reinterpret_cast<int32_t*>(trig + hmax * hmax);
+    // MX: the first digit's histogram is formed as the bins are, past the
+    // block and twiddles and past the rest of the scratch, which overlays them
+    const size_t mx_ovl = 64 + (size_t)d->T * 8 + (size_t)s1 * d->depth * 4;
+    int32_t* hist = MX ? reinterpret_cast<int32_t*>(smem + max((size_t)Pmax * 8 + (size_t)s1 * 8, mx_ovl))
+                       : reinterpret_cast<int32_t*>(trig + hmax * hmax);
     int32_t* part = MX ? reinterpret_cast<int32_t*>(smem) : hist + kSelBins;
     uint64_t* hk = reinterpret_cast<uint64_t*>(part + 16);   // [T]
     int32_t* cl = reinterpret_cast<int32_t*>(hk + d->T);        // [s1 depth]

@@ -251,9 +251,10 @@ size_t dft_lds_bytes(const SigDesc& d) {
 }
 
 size_t dft_mx_lds_bytes(const SigDesc& d, int jhi) {
-    // the block (8 B per bin), the s1 twiddles and the selection's first
-    // histogram; once step B has read the block, the scan partials, T heavy
-    // keys and class lists take its place
+    // the block (8 B per bin) and the s1 twiddles, over which the selection's
+    // scan partials, T heavy keys and class lists go once step B has read the
+    // block (past it when they need more); then the selection's first
+    // histogram, formed as the bins are
     const size_t block = (size_t)d.P[jhi - 1] * 8 + (size_t)d.s1 * 8;
     const size_t scratch = 64 + (size_t)d.T * 8 + (size_t)d.s1 * d.depth * 4;
     return std::max(block, scratch) + (size_t)kSelBins * 4 + 64;

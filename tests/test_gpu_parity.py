@@ -393,6 +393,44 @@ def test_split_matrix_core_path_equals_in_lds_matrix_core_path(gpu, N, s, snr, k
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("kind", ["impulse", "zero", "tone"])
+def test_matrix_core_selection_forms_agree(gpu, kind):
+    """Selection at inputs whose bins are degenerate (an impulse or a zero
+    input: every bin of a block has one magnitude, so the T-th largest key is
+    decided by the bin index; a pure tone: one heavy bin per block, the rest
+    rounding noise): the in-LDS matrix-core kernel (radix passes over its
+    registers) and the split path (candidate list in LDS, passes over E when
+    it overflows) agree bit for bit on bins, heavy sets and outputs, for
+    single calls and a batch of four."""
+    N, s = 2 ** 16, 40
+    fs = []
+    for i in range(4):
+        x = np.zeros(N, np.complex64)
+        if kind == "impulse":
+            x[1000 * i + 7] = 1.0
+        elif kind == "tone":   # one frequency: one heavy bin per block, the rest rounding noise
+            x[:] = np.exp(2j * np.pi * (123 + 17 * i) * np.arange(N) / N).astype(np.complex64)
+        fs.append(dev(x))
+    say("matrix-core selection forms", kind)
+    res = []
+    for path in (3, 4):
+        plan = gpu.Plan(N, s, dft_path=path)
+        outs, counts = gpu.execute_many([plan] * 4, fs)
+        torch.cuda.synchronize()
+        single = []
+        for i, f in enumerate(fs):
+            w, c, n = plan.execute(f)
+            torch.cuda.synchronize()
+            assert int(counts[i].item()) == int(n.item()), (path, i)
+            assert np.array_equal(outs[i][0].cpu().numpy(), w.cpu().numpy()), (path, i)
+            assert np.array_equal(outs[i][1].cpu().numpy(), c.cpu().numpy()), (path, i)
+            single.append((w.cpu().numpy(), c.cpu().numpy(), plan.fetch(gpu.FETCH_BINS), plan.fetch(gpu.FETCH_HEAVY)))
+        res.append(single)
+    for a, b in zip(res[0], res[1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("kind", ["noise", "impulse"])
 def test_split_selection_variants_agree(gpu, kind):
     """The split path's selection has three forms: keys read once into LDS
