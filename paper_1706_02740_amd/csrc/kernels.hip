@@ -223,7 +223,10 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
 //   S_b = exp(2 pi i q_b u / N) * sum_i f[(j' + i) mod N] W(u - i) exp(-2 pi i q_b i / N)
 // with W(v) = exp(-v^2 / (2 sigma_t^2)) / (2 pi sigma_t) (the periodized Gaussian
 // divided by N, eq. Def_Periodic_Gaussian) and the second phasor from the plan's
-// exact table.  The node phasors exp(2 pi i q_b u / N) follow q_{b+1} - q_b = 2L:
+// exact table.  The phasors of taps i and -i are conjugate, so the sum takes
+// the taps in pairs (two complex products' worth of FMAs per pair instead of
+// four; the table's entries for i < 0 are not read).  The node phasors
+// exp(2 pi i q_b u / N) follow q_{b+1} - q_b = 2L:
 // evaluated directly every kPhaseAnchor bands and by one complex product per
 // band in between.  TAPS > 0 fixes 2 kappa + 1 at compile time (the window is
 // loaded before any arithmetic); TAPS == 0 reads it from the plan.  Both forms
@@ -359,7 +362,16 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < TAPS; ++i) x[i] = make_float2(x[i].x * w[i], x[i].y * w[i]);
-        // two bands per pass (their 4 TAPS table values fit the scalar registers);
+        // the taps folded in pairs: the phasors of offsets o and -o are
+        // conjugate, so y_o T_o + y_-o conj(T_o) = (Re T A.x - Im T B.y,
+        // Re T A.y + Im T B.x) with A = y_o + y_-o, B = y_o - y_-o, and T_0 = 1
+        float2 fa[KP], fb[KP];
+#pragma unroll
+        for (int o = 1; o <= KP; ++o) {
+            fa[o - 1] = make_float2(x[KP + o].x + x[KP - o].x, x[KP + o].y + x[KP - o].y);
+            fb[o - 1] = make_float2(x[KP + o].x - x[KP - o].x, x[KP + o].y - x[KP - o].y);
+        }
+        // two bands per pass (their 2 kappa table values fit the scalar registers);
         // band phasor exp(2 pi i u q_b / N): anchored every kPhaseAnchor bands,
         // rotated by exp(2 pi i u 2L / N) in between
         float sn, cs;
@@ -367,16 +379,16 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
         const float2 step = make_float2(cs, sn);
         float2 ph = make_float2(1.f, 0.f);
         for (int b0 = 0; b0 < Q; b0 += 2) {
-            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * TAPS;   // zero-padded past Q
+            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * TAPS + KP;   // zero-padded past Q
             float2 acc[2];
 #pragma unroll
             for (int bb = 0; bb < 2; ++bb) {
-                acc[bb] = make_float2(0.f, 0.f);
+                acc[bb] = x[KP];
 #pragma unroll
-                for (int i = 0; i < TAPS; ++i) {
-                    const float2 t = ld2(tab + bb * TAPS + i);
-                    acc[bb].x = fmaf(x[i].x, t.x, fmaf(-x[i].y, t.y, acc[bb].x));
-                    acc[bb].y = fmaf(x[i].x, t.y, fmaf(x[i].y, t.x, acc[bb].y));
+                for (int o = KP; o >= 1; --o) {   // the outer taps first
+                    const float2 t = ld2(tab + bb * TAPS + o);
+                    acc[bb].x = fmaf(t.x, fa[o - 1].x, fmaf(-t.y, fb[o - 1].y, acc[bb].x));
+                    acc[bb].y = fmaf(t.x, fa[o - 1].y, fmaf(t.y, fb[o - 1].x, acc[bb].y));
                 }
             }
 #pragma unroll
@@ -397,13 +409,13 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
         }
     } else {
         // the same weights as the compile-time kernels, bit for bit: r^|o| by
-        // |o| multiplications from 1 in the same order
+        // |o| multiplications from 1 in the same order, e0 times the Gaussian
+        // factor first
         const float e0 = wnorm * expf(-u * u * inv2sig2);
         const float r = expf(2.0f * u * inv2sig2);
         const float ri = expf(-2.0f * u * inv2sig2);
-        auto weight = [&](int i) {
-            const int o = i - kappa;
-            const float gt = taps <= kFastTaps ? d->gtap[i] : expf(-(float)(o * o) * inv2sig2);
+        auto weight = [&](int o) {
+            const float gt = taps <= kFastTaps ? d->gtap[kappa + o] : expf(-(float)(o * o) * inv2sig2);
             if (o == 0) return e0 * gt;
             const float rr = o > 0 ? r : ri;
             float pw = 1.0f;
@@ -414,27 +426,53 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
         const int64_t jc = jp + sh;   // window centre
         const bool interior = (jc - kappa >= 0) && (jc + kappa < N);
         GLOBAL float2* __restrict__ S = glb(sh ? io.S2 : io.S) + soff;
+        auto yv = [&](int o) {   // the windowed value at offset o of the window
+            int64_t idx = jc + o;
+            if (!interior) {
+                if (idx < 0) idx += N;
+                else if (idx >= N) idx -= N;
+            }
+            const float w = weight(o);
+            const float2 fv = ld2(f + idx);
+            return make_float2(fv.x * w, fv.y * w);
+        };
         for (int b0 = 0; b0 < Q; b0 += kBandChunk) {
             const int nb = min(kBandChunk, Q - b0);
             float2 acc[kBandChunk];
+            if (taps <= kFastTaps) {
+                const float2 y0 = yv(0);
 #pragma unroll
-            for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = make_float2(0.f, 0.f);
-            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * taps;
-            for (int i = 0; i < taps; ++i) {
-                int64_t idx = jc - kappa + i;
-                if (!interior) {
-                    if (idx < 0) idx += N;
-                    else if (idx >= N) idx -= N;
+                for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = y0;
+            }
+            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * taps + kappa;
+            if (taps <= kFastTaps) {
+                // taps folded in conjugate pairs, the outer ones first, as in the
+                // compile-time forms (a batch of several widths runs this kernel)
+                for (int o = kappa; o >= 1; --o) {
+                    const float2 yp = yv(o), ym = yv(-o);
+                    const float2 fa = make_float2(yp.x + ym.x, yp.y + ym.y);
+                    const float2 fb = make_float2(yp.x - ym.x, yp.y - ym.y);
+#pragma unroll
+                    for (int bb = 0; bb < kBandChunk; ++bb) {   // zero-padded table: no guard
+                        const float2 t = ld2(tab + bb * taps + o);
+                        acc[bb].x = fmaf(t.x, fa.x, fmaf(-t.y, fb.y, acc[bb].x));
+                        acc[bb].y = fmaf(t.x, fa.y, fmaf(t.y, fb.x, acc[bb].y));
+                    }
                 }
-                const float w = weight(i);
-                const float2 fv = ld2(f + idx);
-                const float xr = fv.x * w;
-                const float xi = fv.y * w;
+            } else {
+                // wider windows (no compile-time form): every tap with its own
+                // table entry, the window read in order (measured: the folded
+                // pairs, read from both ends, took twice as long at 45 taps)
 #pragma unroll
-                for (int bb = 0; bb < kBandChunk; ++bb) {   // zero-padded table: no guard
-                    const float2 t = ld2(tab + bb * taps + i);
-                    acc[bb].x = fmaf(xr, t.x, fmaf(-xi, t.y, acc[bb].x));
-                    acc[bb].y = fmaf(xr, t.y, fmaf(xi, t.x, acc[bb].y));
+                for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = make_float2(0.f, 0.f);
+                for (int o = -kappa; o <= kappa; ++o) {
+                    const float2 y = yv(o);
+#pragma unroll
+                    for (int bb = 0; bb < kBandChunk; ++bb) {
+                        const float2 t = ld2(tab + bb * taps + o);
+                        acc[bb].x = fmaf(y.x, t.x, fmaf(-y.y, t.y, acc[bb].x));
+                        acc[bb].y = fmaf(y.x, t.y, fmaf(y.y, t.x, acc[bb].y));
+                    }
                 }
             }
             store_bands(S, P, b0, nb, acc, u, rate, step_rate);
