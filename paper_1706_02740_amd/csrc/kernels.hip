@@ -930,15 +930,44 @@ __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
     __syncthreads();
 }
 
-// Row FFTs: two register passes for s1 = 64 and 128 (at most ROWS128 and
-// ROWS64 rows), else the radix-2/4 LDS passes.  The in-LDS and the split
-// kernels take the same branch for a plan, so their results stay bitwise equal.
-template <int NT, int ROWS128, int ROWS64, bool SWZ = false>
+// Row FFTs: two register passes for s1 = 64, 128 and 256 (ROWS256 = 0: no
+// such branch compiled), else the radix-2/4 LDS passes.  Without CHUNKED the
+// rows are at most ROWS64, ROWS128 or ROWS256; with it they are taken in
+// chunks of that many (multiples of 4).  A row's arithmetic does not depend
+// on the chunk it is in, so the in-LDS kernels (a whole block) and the split
+// path's row kernel (a few rows) give bitwise equal rows.
+template <int NT, int ROWS128, int ROWS64, bool SWZ = false, int ROWS256 = 0, bool CHUNKED = false>
 __device__ __forceinline__ void fft_rows(float2* buf, int rows, int s1, int lg, const float2* tw) {
     static_assert(!SWZ || (ROWS128 >= 64 && ROWS64 >= 64), "the swizzled layout needs the register passes");
-    if (s1 == 128 && rows <= ROWS128) fft_rows_2pass<NT, 16, 8, ROWS128, SWZ>(buf, rows, tw);
-    else if (s1 == 64 && rows <= ROWS64) fft_rows_2pass<NT, 8, 8, ROWS64, SWZ>(buf, rows, tw);
-    else fft_rows_lds<NT>(buf, rows, s1, lg, tw);
+    static_assert(ROWS128 % 4 == 0 && ROWS64 % 4 == 0 && ROWS256 % 4 == 0, "chunks keep the row swizzle");
+    if constexpr (ROWS256 > 0) {
+        if (s1 == 256) {
+            if constexpr (CHUNKED) {
+                for (int r0 = 0; r0 < rows; r0 += ROWS256)
+                    fft_rows_2pass<NT, 16, 16, ROWS256, SWZ>(buf + ((size_t)r0 << 8), min(ROWS256, rows - r0), tw);
+            } else {
+                fft_rows_2pass<NT, 16, 16, ROWS256, SWZ>(buf, rows, tw);
+            }
+            return;
+        }
+    }
+    if (s1 == 128) {
+        if constexpr (CHUNKED) {
+            for (int r0 = 0; r0 < rows; r0 += ROWS128)
+                fft_rows_2pass<NT, 16, 8, ROWS128, SWZ>(buf + ((size_t)r0 << 7), min(ROWS128, rows - r0), tw);
+        } else {
+            fft_rows_2pass<NT, 16, 8, ROWS128, SWZ>(buf, rows, tw);
+        }
+    } else if (s1 == 64) {
+        if constexpr (CHUNKED) {
+            for (int r0 = 0; r0 < rows; r0 += ROWS64)
+                fft_rows_2pass<NT, 8, 8, ROWS64, SWZ>(buf + ((size_t)r0 << 6), min(ROWS64, rows - r0), tw);
+        } else {
+            fft_rows_2pass<NT, 8, 8, ROWS64, SWZ>(buf, rows, tw);
+        }
+    } else {
+        fft_rows_lds<NT>(buf, rows, s1, lg, tw);
+    }
 }
 
 // Cosine/sine table of a p-point step (host-computed per modulus), copied to
@@ -1587,7 +1616,8 @@ __global__ void __launch_bounds__(kDftThreads) k_dft(BatchArgs a) {
         load_trig<NT>(trig, h, glb(d->trig) + d->trig_off[j]);
     }
     __syncthreads();
-    fft_rows<NT, 64, 64, MX>(buf, p, s1, lg, tw);
+    // MX: p <= 63 rows in one pass; VALU: whole blocks of any height, in chunks
+    fft_rows<NT, 64, 64, MX, MX ? 0 : 64, !MX>(buf, p, s1, lg, tw);
 
     // step B
     GLOBAL float2* __restrict__ E = glb(shifted ? io.E2 : io.E) + base;
@@ -1801,12 +1831,8 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
         tw[i + (s1 >> 1)] = make_float2(-w.x, -w.y);
     }
     __syncthreads();
-    // rows are transformed independently: take the in-LDS kernel's branch for
-    // this plan (two register passes when s1 is 64 or 128 and p <= 64)
-    if ((s1 == 128 || s1 == 64) && p <= 64)
-        fft_rows<kThreads, kRowElems / 128, kRowElems / 64>(buf, rows, s1, lg, tw);
-    else
-        fft_rows_lds<kThreads>(buf, rows, s1, lg, tw);
+    // rows are transformed independently, as in the in-LDS kernels
+    fft_rows<kThreads, kRowElems / 128, kRowElems / 64, false, kRowElems / 256>(buf, rows, s1, lg, tw);
     GLOBAL float2* __restrict__ X = glb(shifted ? io.E2 : io.E) + base;   // the bins' buffer holds the step-A result
     for (int i = tid; i < n; i += kThreads) st2s(X + i, buf[i]);
 }
