@@ -276,6 +276,10 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
             band[(size_t)b * taps + i] = make_float2((float)cos(ang), (float)sin(ang));
         }
     }
+    std::vector<float2> bandt(n_band, make_float2(0.f, 0.f));   // [taps][Qpad]
+    for (int b = 0; b < d.Q; ++b)
+        for (int i = 0; i < taps; ++i) bandt[(size_t)i * Qpad + b] = band[(size_t)b * taps + i];
+    d.qpad = Qpad;
     for (size_t k = 0; k < n_tws1; ++k) {
         const double ang = -2.0 * M_PI * (double)k / (double)d.s1;
         tws1[k] = make_float2((float)cos(ang), (float)sin(ang));
@@ -358,7 +362,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     const size_t b_band = al(n_band * 8), b_tws1 = al(n_tws1 * 8), b_twp = al(n_twp * 8), b_rate = al((size_t)Qpad * 4);
     const size_t b_trig = al(n_trig * 8), b_mxa = al(n_mxa * 8), b_mxc = al(n_mxc * 8);
     const size_t b_gmxa = al(n_gmxa * 4), b_gmxg = al(n_gmxg * 4);
-    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa + b_mxc + b_gmxa + b_gmxg;
+    const size_t tbytes = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa + b_mxc + b_gmxa + b_gmxg + b_band;
     hipError_t e = hipMalloc(&pl->tables, tbytes);
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(tables) failed"); }
     char* tb = static_cast<char*>(pl->tables);
@@ -372,6 +376,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     const size_t o_gmx = b_band + b_tws1 + b_twp + b_rate + b_trig + b_mxa + b_mxc;
     d.gmx_a = n_gmxa ? reinterpret_cast<const float*>(tb + o_gmx) : nullptr;
     d.gmx_g = n_gmxg ? reinterpret_cast<const float*>(tb + o_gmx + b_gmxa) : nullptr;
+    d.bandtab_t = reinterpret_cast<const float2*>(tb + o_gmx + b_gmxa + b_gmxg);
     e = hipMemcpy(tb, band.data(), n_band * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band, tws1.data(), n_tws1 * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tb + b_band + b_tws1, twp.data(), n_twp * 8, hipMemcpyHostToDevice);
@@ -385,6 +390,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && n_gmxa) e = hipMemcpy(tb + o_gmx, gmxa.data(), n_gmxa * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess && n_gmxg) e = hipMemcpy(tb + o_gmx + b_gmxa, gmxg.data(), n_gmxg * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tb + o_gmx + b_gmxa + b_gmxg, bandt.data(), n_band * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) { sft_plan_destroy(pl); return hip_fail(e, "hipMemcpy(tables)"); }
     e = hipMalloc(&pl->ddesc, sizeof(SigDesc));
     if (e != hipSuccess) { sft_plan_destroy(pl); return fail(SFT_ENOMEM, "hipMalloc(descriptor) failed"); }

@@ -444,7 +444,9 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
 #pragma unroll
                 for (int bb = 0; bb < kBandChunk; ++bb) acc[bb] = y0;
             }
-            const CONSTANT float2* tab = cst(d->bandtab) + (size_t)b0 * taps + kappa;
+            // the transposed table: a tap's kBandChunk bands are one 128-byte piece
+            const int qpad = d->qpad;
+            const CONSTANT float2* tab = cst(d->bandtab_t) + (size_t)kappa * qpad + b0;
             if (taps <= kFastTaps) {
                 // taps folded in conjugate pairs, the outer ones first, as in the
                 // compile-time forms (a batch of several widths runs this kernel)
@@ -454,7 +456,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                     const float2 fb = make_float2(yp.x - ym.x, yp.y - ym.y);
 #pragma unroll
                     for (int bb = 0; bb < kBandChunk; ++bb) {   // zero-padded table: no guard
-                        const float2 t = ld2(tab + bb * taps + o);
+                        const float2 t = ld2(tab + o * qpad + bb);
                         acc[bb].x = fmaf(t.x, fa.x, fmaf(-t.y, fb.y, acc[bb].x));
                         acc[bb].y = fmaf(t.x, fa.y, fmaf(t.y, fb.x, acc[bb].y));
                     }
@@ -469,7 +471,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(BatchArgs a) {
                     const float2 y = yv(o);
 #pragma unroll
                     for (int bb = 0; bb < kBandChunk; ++bb) {
-                        const float2 t = ld2(tab + bb * taps + o);
+                        const float2 t = ld2(tab + o * qpad + bb);
                         acc[bb].x = fmaf(y.x, t.x, fmaf(-y.y, t.y, acc[bb].x));
                         acc[bb].y = fmaf(y.x, t.y, fmaf(y.y, t.x, acc[bb].y));
                     }

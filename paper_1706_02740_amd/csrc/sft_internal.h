@@ -75,6 +75,8 @@ struct SigDesc {
     int32_t lo_mod_P[kMaxK];   // lo mod P_j, in [0, P_j)
     // device tables owned by the plan
     const float2* bandtab;   // [Q][taps]: exp(-2 pi i ((q_b (i - kappa)) mod N) / N)
+    const float2* bandtab_t; // [taps][Qpad]: the same transposed, zero past Q (Qpad: Q up to whole kBandChunk)
+    int32_t qpad;
     const float2* tw_s1;     // [s1/2]: exp(-2 pi i k / s1)
     const float2* tw_p;      // concatenated [p_j]: exp(-2 pi i m / p_j)
     const float* rate;       // [Q]: q_b / N, the per-node band phase rate in turns
