@@ -862,8 +862,9 @@ __device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
 // that pass 2 reads R1 values per thread without LDS bank conflicts.
 // SWZ: the result X[k] of a row goes to position k ^ swz_col(row) instead of k
 // (the layout the matrix-core p-point step reads without bank conflicts).
-// tw: LDS exp(-2 pi i m / S), m < S.
-template <int NT, int R1, int R2, int ROWSMAX, bool SWZ = false>
+// tw: LDS exp(-2 pi i m / (S TWS)), m < S TWS (TWS > 1: a longer transform's
+// table, read at every TWS-th entry).
+template <int NT, int R1, int R2, int ROWSMAX, bool SWZ = false, int TWS = 1>
 __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
     constexpr int S = R1 * R2;
     constexpr int IT1 = (ROWSMAX * R1 + NT - 1) / NT;
@@ -883,7 +884,7 @@ __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
             dft_reg<R2>(z[it]);
 #pragma unroll
             for (int k2 = 1; k2 < R2; ++k2) {
-                const float2 w = tw[n1 * k2];
+                const float2 w = tw[n1 * k2 * TWS];
                 const float2 b = z[it][k2];
                 z[it][k2] = cmul(b, w);
             }
@@ -932,16 +933,94 @@ __device__ void fft_rows_2pass(float2* buf, int rows, const float2* tw) {
     __syncthreads();
 }
 
+// Length-S row FFTs for S = 8 A (A = 64, 128, 256: s1 = 512, 1024, 2048) in
+// register passes.  With n = m + A n3 and k = 8 k' + k3,
+//   X[8 k' + k3] = sum_m W_A^(m k') [W_S^(m k3) sum_n3 x[m + A n3] W_8^(n3 k3)]:
+// an 8-point DFT and twiddles per (row, m), written to sub-row k3 of the row
+// (position k3 A + m); the A-point transforms of the 8 sub-rows by the two
+// register passes (their twiddles every 8th entry of the S-point table); then
+// the permutation to natural order through registers.  At most ROWS rows.
+template <int NT, int A, int ROWS>
+__device__ void fft_rows_3pass(float2* buf, int rows, const float2* tw) {
+    constexpr int S = 8 * A;
+    constexpr int IT0 = (ROWS * A + NT - 1) / NT;
+    constexpr int IT3 = (ROWS * S + NT - 1) / NT;
+    constexpr int R1 = A == 64 ? 8 : 16, R2 = A == 256 ? 16 : 8;
+    static_assert(R1 * R2 == A, "sub-row length");
+    const int tid = (int)threadIdx.x;
+    float2 z[IT0][8];
+#pragma unroll
+    for (int it = 0; it < IT0; ++it) {
+        const int item = tid + it * NT;
+        if (item < rows * A) {
+            const int row = item / A, m = item % A;
+            const float2* x = buf + row * S + m;
+#pragma unroll
+            for (int n3 = 0; n3 < 8; ++n3) z[it][n3] = x[n3 * A];
+            dft_reg<8>(z[it]);
+#pragma unroll
+            for (int k3 = 1; k3 < 8; ++k3) z[it][k3] = cmul(z[it][k3], tw[m * k3]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT0; ++it) {
+        const int item = tid + it * NT;
+        if (item < rows * A) {
+            const int row = item / A, m = item % A;
+#pragma unroll
+            for (int k3 = 0; k3 < 8; ++k3) buf[row * S + k3 * A + m] = z[it][k3];
+        }
+    }
+    __syncthreads();
+    fft_rows_2pass<NT, R1, R2, ROWS * 8, false, 8>(buf, rows * 8, tw);
+    float2 v[IT3];
+#pragma unroll
+    for (int it = 0; it < IT3; ++it) {
+        const int idx = tid + it * NT;
+        if (idx < rows * S) {
+            const int row = idx / S, k = idx % S;
+            v[it] = buf[row * S + (k & 7) * A + (k >> 3)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT3; ++it) {
+        const int idx = tid + it * NT;
+        if (idx < rows * S) buf[idx] = v[it];
+    }
+    __syncthreads();
+}
+
 // Row FFTs: two register passes for s1 = 64, 128 and 256 (ROWS256 = 0: no
-// such branch compiled), else the radix-2/4 LDS passes.  Without CHUNKED the
-// rows are at most ROWS64, ROWS128 or ROWS256; with it they are taken in
-// chunks of that many (multiples of 4).  A row's arithmetic does not depend
-// on the chunk it is in, so the in-LDS kernels (a whole block) and the split
-// path's row kernel (a few rows) give bitwise equal rows.
-template <int NT, int ROWS128, int ROWS64, bool SWZ = false, int ROWS256 = 0, bool CHUNKED = false>
+// such branch compiled), three for s1 = 512 ... 2048 where BIGELEMS > 0
+// (BIGELEMS / s1 rows at a time), else the radix-2/4 LDS passes.  Without
+// CHUNKED the rows are at most ROWS64, ROWS128 or ROWS256; with it they are
+// taken in chunks of that many (multiples of 4).  A row's arithmetic does not
+// depend on the chunk it is in, so the in-LDS kernels (a whole block) and the
+// split path's row kernel (a few rows) give bitwise equal rows up to s1 = 256.
+// Only the row kernel takes the three passes (compiled into the in-LDS VALU
+// kernel they raised it from 116 to 169 VGPRs): for s1 >= 512 the in-LDS
+// VALU kernel keeps the LDS passes and the two paths agree to rounding.
+template <int NT, int ROWS128, int ROWS64, bool SWZ = false, int ROWS256 = 0, bool CHUNKED = false, int BIGELEMS = 0>
 __device__ __forceinline__ void fft_rows(float2* buf, int rows, int s1, int lg, const float2* tw) {
     static_assert(!SWZ || (ROWS128 >= 64 && ROWS64 >= 64), "the swizzled layout needs the register passes");
     static_assert(ROWS128 % 4 == 0 && ROWS64 % 4 == 0 && ROWS256 % 4 == 0, "chunks keep the row swizzle");
+    if constexpr (BIGELEMS > 0) {   // s1 = 512, 1024, 2048: three register passes, BIGELEMS / s1 rows at a time
+        if (s1 >= 512 && s1 <= 2048) {
+            const int per = BIGELEMS >> lg;
+#pragma unroll 1
+            for (int r0 = 0; r0 < rows; r0 += per) {
+                float2* b = buf + ((size_t)r0 << lg);
+                const int n = min(per, rows - r0);
+                if (s1 == 512) fft_rows_3pass<NT, 64, BIGELEMS / 512>(b, n, tw);
+                else if (s1 == 1024) fft_rows_3pass<NT, 128, BIGELEMS / 1024>(b, n, tw);
+                else fft_rows_3pass<NT, 256, BIGELEMS / 2048>(b, n, tw);
+                if (!CHUNKED) break;
+            }
+            return;
+        }
+    }
     if constexpr (ROWS256 > 0) {
         if (s1 == 256) {
             if constexpr (CHUNKED) {
@@ -1834,7 +1913,7 @@ __global__ void __launch_bounds__(kThreads) k_dft_rows(BatchArgs a) {
     }
     __syncthreads();
     // rows are transformed independently, as in the in-LDS kernels
-    fft_rows<kThreads, kRowElems / 128, kRowElems / 64, false, kRowElems / 256>(buf, rows, s1, lg, tw);
+    fft_rows<kThreads, kRowElems / 128, kRowElems / 64, false, kRowElems / 256, false, kRowElems>(buf, rows, s1, lg, tw);
     GLOBAL float2* __restrict__ X = glb(shifted ? io.E2 : io.E) + base;   // the bins' buffer holds the step-A result
     for (int i = tid; i < n; i += kThreads) st2s(X + i, buf[i]);
 }

@@ -87,6 +87,11 @@ INTERMEDIATE_CASES = [
     ("gvalu_n2e14_s8_theory", 2 ** 14, 8, None, {"preset": 2, "gather_path": 1}, 3),
     ("gmx_n98304_s12_dmsft4", 3 * 2 ** 15, 12, 40.0, {"preset": 1, "gather_path": 2}, 2),
     ("gmx_n64_s64", 64, 64, None, {"gather_path": 2}, 5),   # every window wraps
+    # s1 = 512, 1024, 2048: the split path's row kernel in three register passes
+    # (8-point DFTs, then the two passes of the 64-, 128- or 256-point sub-rows)
+    ("split_s1_512_n2e16_s150_30db", 2 ** 16, 150, 30.0, {"dft_path": 2}, 9),
+    ("splitmx_s1_1024_n2e16_s400_30db", 2 ** 16, 400, 30.0, {}, 10),
+    ("split_s1_2048_n2e16_s800_30db", 2 ** 16, 800, 30.0, {"dft_path": 2}, 11),
 ]
 
 
