@@ -86,8 +86,10 @@ extern "C" {
  * step on the matrix cores (s1 >= 64, every (p_j - 1)/2 <= 47); 0 = automatic:
  * 3 when it covers the plan, else 1 when two of its workgroups fit a CU's
  * LDS, else 4 when it covers the plan, else 2 (sft_plan_info.dft_path reports
- * the choice).  Paths 1 and 2 give bitwise equal results, and so do paths 3
- * and 4; the matrix-core paths sum the p-point step in another order.
+ * the choice).  Paths 1 and 2 give bitwise equal results for s1 <= 256 (for
+ * s1 >= 512 their row FFTs differ in order, results agree to FP32 rounding),
+ * and so do paths 3 and 4; the matrix-core paths sum the p-point step in
+ * another order.
  * gather_path chooses the filtered-sample kernel: 1 = band sums on the vector
  * ALUs (one node per lane), 2 = band sums as a product on the matrix cores
  * (s1 >= 16, up to 64 bands and 63 taps), 0 = automatic (2 when it covers the plan;

@@ -11,9 +11,9 @@ shape (N, s, parameters) and a batch size the tuner times, on a synthetic
 input with HIP events on the launch stream, every (dft_path, gather_path)
 pair the library accepts with the automatic split, then every split of the
 fastest pair when that pair runs path 3, and keeps the fastest.  All
-configurations compute the same transform (paths 1 and 2 bitwise equal, as
-are 3 and 4 and every split; the gathers and the two path families differ
-by rounding order).  Results are cached per device architecture, plan shape
+configurations compute the same transform (paths 1 and 2 bitwise equal up
+to s1 = 256, as are 3 and 4 and every split; the gathers, the two path
+families and paths 1 and 2 at s1 >= 512 differ by rounding order).  Results are cached per device architecture, plan shape
 and batch-size class in a JSON file (``$SFT_TUNE_CACHE``, default
 ``~/.cache/paper_1706_02740_amd/tune.json``), so a shape is measured once.
 """
