@@ -224,8 +224,8 @@ __device__ int block_exclusive_scan(int32_t* data, int n, int32_t* scratch) {
 // with W(v) = exp(-v^2 / (2 sigma_t^2)) / (2 pi sigma_t) (the periodized Gaussian
 // divided by N, eq. Def_Periodic_Gaussian) and the second phasor from the plan's
 // exact table.  The phasors of taps i and -i are conjugate, so the sum takes
-// the taps in pairs (two complex products' worth of FMAs per pair instead of
-// four; the table's entries for i < 0 are not read).  The node phasors
+// the taps in pairs (four FMAs per pair and band instead of eight; the
+// table's entries for i < 0 are not read).  The node phasors
 // exp(2 pi i q_b u / N) follow q_{b+1} - q_b = 2L:
 // evaluated directly every kPhaseAnchor bands and by one complex product per
 // band in between.  TAPS > 0 fixes 2 kappa + 1 at compile time (the window is
