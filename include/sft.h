@@ -191,7 +191,8 @@ SFT_API int sft_plan_get_info(const sft_plan_t plan, sft_plan_info* out);
 SFT_API int sft_plan_footprint(const sft_plan_t plan, size_t* bytes_device);
 
 /* Device workspace one transform of this plan needs (filtered samples,
- * bins, heavy-bin tables, band results): the size of its sft_execute
+ * bins, heavy-bin tables, band results; for the split path with matrix-core
+ * columns also the per-block digit histograms of its selection): the size of its sft_execute
  * workspace and of its slice of a batch's workspace.  Host only. */
 SFT_API int sft_plan_workspace_bytes(const sft_plan_t plan, size_t* bytes);
 
