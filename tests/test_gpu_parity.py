@@ -437,15 +437,17 @@ def test_matrix_core_selection_forms_agree(gpu, kind):
 
 
 @pytest.mark.parametrize("kind", ["noise", "impulse"])
-def test_split_selection_variants_agree(gpu, kind):
+@pytest.mark.parametrize("path", [2, 4])
+def test_split_selection_variants_agree(gpu, kind, path):
     """The split path's selection has three forms: keys read once into LDS
     (a launch of at most one block per CU: a single transform), a candidate
     list of the keys at or above the T-th largest key's bucket (larger
     launches), and passes over E (when the list overflows, as for an impulse,
-    whose bins all have one magnitude).  A batch of four and the single
-    calls give the same outputs bit for bit."""
+    whose bins all have one magnitude).  With the matrix-core column kernel
+    (path 4) the list's first histogram comes from the column kernel.  A
+    batch of four and the single calls give the same outputs bit for bit."""
     N, s = 2 ** 18, 64
-    plan = gpu.Plan(N, s, dft_path=2)
+    plan = gpu.Plan(N, s, dft_path=path)
     if kind == "noise":
         fs = [dev(siggen.sparse_signal(N, s, seed=40 + i, snr_db=10.0).f32) for i in range(4)]
     else:
@@ -455,7 +457,7 @@ def test_split_selection_variants_agree(gpu, kind):
             imp[:] = 0
             imp[1000 * i] = 1.0
             fs.append(dev(imp))
-    say("split selection variants", kind)
+    say("split selection variants", kind, path)
     outs, counts = gpu.execute_many([plan] * 4, fs)
     torch.cuda.synchronize()
     for i, f in enumerate(fs):
