@@ -2196,13 +2196,16 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
                 const uint32_t h = hi_of(ev[u]);
                 const bool take = i < P && ((h >> 21) & (kSelBins - 1)) >= dig;
                 const uint64_t m = __ballot(take);
-                int wb = 0;
-                if (lane == 0 && m) wb = atomicAdd(&sh_nc, __popcll(m));
-                wb = __shfl(wb, 0);
-                if (take) {
-                    const int pos = wb + __popcll(m & ltm);
-                    if (pos < cap)
-                        cand[pos] = ((uint64_t)h << 32) | (uint64_t)(0xffffffffu - pfa_bin(i, lg, s1, (uint32_t)P, cA, cB));
+                if (m) {   // wave-uniform: most bins are below the bucket
+                    int wb = 0;
+                    if (lane == 0) wb = atomicAdd(&sh_nc, __popcll(m));
+                    wb = __builtin_amdgcn_readfirstlane(wb);   // lane 0's (every lane is active here)
+                    if (take) {
+                        const int pos = wb + __popcll(m & ltm);
+                        if (pos < cap)
+                            cand[pos] = ((uint64_t)h << 32) |
+                                        (uint64_t)(0xffffffffu - pfa_bin(i, lg, s1, (uint32_t)P, cA, cB));
+                    }
                 }
             }
         }
