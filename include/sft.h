@@ -311,6 +311,12 @@ SFT_API int sft_plan_status(sft_plan_t plan, int32_t* flags);
  *                      double im) records; see the library documentation.
  *   SFT_FETCH_SAMPLES_SHIFTED, SFT_FETCH_BINS_SHIFTED  (SFT_IDENT_PHASE plans)
  *                      as SAMPLES and BINS for the nodes moved one grid step.
+ *   SFT_FETCH_CLASSES  int32[K * Q * s1 * depth]: per block (j, b) and residue
+ *                      class c (h mod s1), at ((j*Q + b)*s1 + c)*depth + e, the
+ *                      e-th heaviest heavy bin of the class (larger |E|^2
+ *                      first, the lower h first on equal |E|^2), -1 where the
+ *                      class holds fewer than e + 1 heavy bins: the lists
+ *                      that the CRT step combines.
  * bytes_needed (may be NULL) receives the size; dst may be NULL to query.
  */
 #define SFT_FETCH_SAMPLES 0
@@ -319,6 +325,7 @@ SFT_API int sft_plan_status(sft_plan_t plan, int32_t* flags);
 #define SFT_FETCH_BANDS   3
 #define SFT_FETCH_SAMPLES_SHIFTED 4
 #define SFT_FETCH_BINS_SHIFTED    5
+#define SFT_FETCH_CLASSES         6
 SFT_API int sft_plan_fetch(const sft_plan_t plan, int32_t what, void* dst, size_t bytes,
                    size_t* bytes_needed);
 

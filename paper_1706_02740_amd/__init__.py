@@ -44,6 +44,7 @@ FETCH_HEAVY = 2
 FETCH_BANDS = 3
 FETCH_SAMPLES_SHIFTED = 4
 FETCH_BINS_SHIFTED = 5
+FETCH_CLASSES = 6
 
 KERNEL_GATHER = 0
 KERNEL_DFT = 1
@@ -307,7 +308,7 @@ class Plan:
         _check(lib.sft_plan_fetch(self._h, int(what), ctypes.c_void_p(buf.ctypes.data), need.value, None))
         if what in (FETCH_SAMPLES, FETCH_BINS, FETCH_SAMPLES_SHIFTED, FETCH_BINS_SHIFTED):
             return buf.view(np.complex64)
-        if what == FETCH_HEAVY:
+        if what in (FETCH_HEAVY, FETCH_CLASSES):
             return buf.view(np.int32)
         Q, s = self.info["Q"], self.s
         counts = buf[: 4 * Q].view(np.int32).copy()

@@ -1037,6 +1037,7 @@ int sft_plan_fetch(const sft_plan_t plan, int32_t what, void* dst, size_t bytes,
             src = what == SFT_FETCH_SAMPLES_SHIFTED ? plan->ws_io.S2 : plan->ws_io.E2;
             need = (size_t)in.Q * in.M * 8;
             break;
+        case SFT_FETCH_CLASSES: src = plan->ws_io.CL; need = (size_t)in.K * in.Q * in.s1 * in.depth * 4; break;
         default: return fail(SFT_EINVAL, "unknown fetch kind");
     }
     if (bytes_needed) *bytes_needed = need;

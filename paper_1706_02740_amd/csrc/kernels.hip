@@ -1247,8 +1247,8 @@ __device__ int block_exclusive_sum(int v, int32_t* part) {
 // contiguous indices [w seg, (w + 1) seg) 64 at a time; a ballot per step
 // gives each heavy bin its rank within the wave, a scan of the per-wave
 // counts its rank in the block, so H comes out in index order without
-// sorting.  Class ranks come from pairwise key comparisons of the heavy
-// (key, index) pairs (hk), split over all threads.
+// sorting.  Class ranks come from key comparisons within each class: for a
+// few heavy bins all pairs, split over all threads; else per class list.
 // scr: LDS int32[kSelBins]; part: LDS int32[NT / 64]; hk: LDS uint64[2 T];
 // cl: LDS int32[s1 * depth].
 template <int NT, class KeyF>
@@ -1323,12 +1323,37 @@ __device__ void emit_heavy(KeyF key, int P, int T, int s1, int depth, uint64_t t
             }
         }
     } else {
+        // Rank each entry within its own class only: the entries of a class
+        // are linked into a list (head in the class's first CL slot, next in
+        // the low word of hk[2 e + 1]; the rank goes to its high word).  An
+        // entry whose class list runs past kWalk entries compares against
+        // all n instead.
+        constexpr int kWalk = 32;
+        for (int e = tid; e < n; e += NT)
+            hk[2 * e + 1] = (uint32_t)atomicExch(&cl[class_of(hk[2 * e]) * depth], e);
+        __syncthreads();
         for (int e = tid; e < n; e += NT) {
             const uint64_t k = hk[2 * e];
             const int cls = class_of(k);
             int r = 0;
-            for (int f = 0; f < n; ++f) r += (class_of(hk[2 * f]) == cls && hk[2 * f] > k) ? 1 : 0;
-            if (r < depth) cl[cls * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
+            int f = cl[cls * depth];
+            for (int st = 0; f >= 0 && st < kWalk; ++st) {
+                r += hk[2 * f] > k ? 1 : 0;
+                f = (int)(uint32_t)hk[2 * f + 1];
+            }
+            if (f >= 0) {
+                r = 0;
+                for (f = 0; f < n; ++f) r += (class_of(hk[2 * f]) == cls && hk[2 * f] > k) ? 1 : 0;
+            }
+            hk[2 * e + 1] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)hk[2 * e + 1];   // the low word stays
+        }
+        __syncthreads();
+        for (int c = tid; c < s1; c += NT) cl[c * depth] = -1;
+        __syncthreads();
+        for (int e = tid; e < n; e += NT) {
+            const int r = (int)(hk[2 * e + 1] >> 32);
+            const uint64_t k = hk[2 * e];
+            if (r < depth) cl[class_of(k) * depth + r] = (int32_t)(0xffffffffu - (uint32_t)(k & 0xffffffffu));
         }
     }
     __syncthreads();

@@ -468,6 +468,99 @@ def test_split_selection_variants_agree(gpu, kind, path):
         assert np.array_equal(outs[i][1].cpu().numpy(), c.cpu().numpy()), i
 
 
+def _round_f32(q):
+    """A non-negative rational rounded to the nearest float32 (ties to even),
+    normal range."""
+    from fractions import Fraction
+    if q == 0:
+        return 0.0
+    n, d = q.numerator, q.denominator
+    e = n.bit_length() - d.bit_length()
+    if (n << max(0, -e)) < (d << max(0, e)):   # q < 2^e
+        e -= 1
+    m = q / Fraction(2) ** (e - 23)            # in [2^23, 2^24)
+    fl = m.numerator // m.denominator
+    rem = m - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2):
+        fl += 1
+    return float(fl) * 2.0 ** (e - 23)
+
+
+def _key_f32(e):
+    """|e|^2 as the selection computes it in FP32: fma(re, re, round(im * im))."""
+    from fractions import Fraction
+    im2 = np.float32(e.imag) * np.float32(e.imag)
+    return _round_f32(Fraction(float(np.float32(e.real))) ** 2 + Fraction(float(im2)))
+
+
+def expected_class_lists(heavy, bins, s1, depth):
+    """Per residue class c (h mod s1), the depth heaviest heavy bins by the
+    FP32 key (larger first, the lower h first on equal keys), -1 padded."""
+    cls = {}
+    for h in heavy.tolist():
+        cls.setdefault(h % s1, []).append(h)
+    out = np.full((s1, depth), -1, np.int32)
+    for c, hs in cls.items():
+        top = sorted(hs, key=lambda h: (-_key_f32(bins[h]), h))[:depth]
+        out[c, :len(top)] = top
+    return out
+
+
+def test_class_lists_with_crowded_classes(gpu):
+    """Residue classes crowded with heavy bins: 96 of the 128 frequencies share
+    one class mod s1 and 24 another, so at N = 2^22 (moduli 29..53) a block's
+    crowded class holds up to about 45 heavy bins, past the 32 that the split
+    selection's per-class walk takes before it compares against every heavy
+    bin.  For the in-LDS kernel (path 1), the split path (2) and the split
+    path with matrix-core columns (4), each block's class lists equal the
+    host's ranking of the fetched bins by the same FP32 key; paths 1 and 2
+    agree bit for bit, and a batch of two gives the single call's outputs."""
+    N, s = 2 ** 22, 128
+    rng = np.random.default_rng(29)
+    lo, _ = siggen.band_limits(N)
+    s1 = 256
+    ks = rng.choice(N // s1, size=120, replace=False)
+    freqs = np.concatenate([5 + s1 * ks[:96], 77 + s1 * ks[96:]]).astype(np.int64)
+    freqs = np.where(freqs > N // 2, freqs - N, freqs)
+    rest = siggen.draw_frequencies(N, 64, rng)
+    rest = rest[~np.isin(rest, freqs)][:8]
+    freqs = np.concatenate([freqs, rest])
+    assert len(set(freqs.tolist())) == s and freqs.min() >= lo
+    f = siggen.add_noise(siggen.synthesize(N, freqs, siggen.draw_coefficients(s, rng)), 30.0, rng)
+    fd = dev(f)
+    res = {}
+    for path in (1, 2, 4):
+        say("crowded class lists, path", path)
+        plan = gpu.Plan(N, s, dft_path=path)
+        info = plan.info
+        assert info["s1"] == s1 and info["T"] > 128 and max(info["primes"]) > 37
+        w, c, n = plan.execute(fd)
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        E_all = plan.fetch(gpu.FETCH_BINS)
+        H_all = plan.fetch(gpu.FETCH_HEAVY)
+        CL_all = plan.fetch(gpu.FETCH_CLASSES)
+        Q, K, depth = info["Q"], info["K"], info["depth"]
+        assert CL_all.size == K * Q * s1 * depth
+        longest = 0
+        for b in (0, Q // 2, Q - 1):
+            for j in range(K):
+                heavy = gpu.heavy_block(plan, H_all, b, j)
+                bins = gpu.bins_natural(plan, E_all, b, j)
+                got = CL_all[(j * Q + b) * s1 * depth: (j * Q + b + 1) * s1 * depth].reshape(s1, depth)
+                assert np.array_equal(got, expected_class_lists(heavy, bins, s1, depth)), (path, b, j)
+                longest = max(longest, int(np.bincount(heavy % s1, minlength=s1).max()))
+        assert longest > 32
+        outs, counts = gpu.execute_many([plan] * 2, [fd, fd])
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert int(counts[i].item()) == int(n.item())
+            assert torch.equal(outs[i][0], w) and torch.equal(outs[i][1], c)
+        res[path] = (w.cpu().numpy(), c.cpu().numpy(), E_all, H_all, CL_all)
+    for x, y in zip(res[1], res[2]):
+        assert np.array_equal(x, y)
+
+
 def test_repeat_runs_are_bitwise_identical(gpu):
     sg = siggen.sparse_signal(2 ** 16, 30, seed=77, snr_db=10.0)
     plan = gpu.Plan(sg.N, sg.s)
