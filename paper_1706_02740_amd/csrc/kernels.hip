@@ -3061,7 +3061,7 @@ hipError_t configure_kernels(int max_lds) {
                          (const void*)k_gather_mx<64, 8>,
                          (const void*)k_merge, (const void*)k_dft_rows,
                          (const void*)k_dft_cols, (const void*)k_dft_cols_mx, (const void*)k_select<kThreads, false>,
-                         (const void*)k_select<kSelLdsThreads, true>};
+                         (const void*)k_select<kSelLdsThreads, false>, (const void*)k_select<kSelLdsThreads, true>};
     for (const void* k : ks) {
         hipFuncAttributes fa;
         int static_lds = 0;
@@ -3158,10 +3158,14 @@ hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t
     // bits) and of the one holding the keys in LDS (above; 0 if some block's
     // keys do not fit).  The LDS-key kernel runs one workgroup per CU: it is
     // taken when the launch has at most one block per CU, where the latency
-    // of a block decides; larger launches keep many workgroups per CU.
+    // of a block decides; larger launches keep many workgroups per CU, or,
+    // where the LDS of a block leaves room for one workgroup per CU only
+    // (large T and s1), run it with 16 waves instead of 4.
     const size_t bytes = lds & 0xffffffffu, kbytes = lds >> 32;
     if (kbytes && blocks <= kSelLdsMaxBlocks)
         hipLaunchKernelGGL((k_select<kSelLdsThreads, true>), dim3(blocks), dim3(kSelLdsThreads), kbytes, st, a);
+    else if (2 * bytes > (size_t)g_max_lds)
+        hipLaunchKernelGGL((k_select<kSelLdsThreads, false>), dim3(blocks), dim3(kSelLdsThreads), bytes, st, a);
     else
         hipLaunchKernelGGL((k_select<kThreads, false>), dim3(blocks), dim3(kThreads), bytes, st, a);
     return hipGetLastError();

@@ -468,6 +468,28 @@ def test_split_selection_variants_agree(gpu, kind, path):
         assert np.array_equal(outs[i][1].cpu().numpy(), c.cpu().numpy()), i
 
 
+@pytest.mark.parametrize("N,s", [(2 ** 22, 512), (2 ** 24, 1024)])
+def test_large_heavy_set_selection_batch_equals_single(gpu, N, s):
+    """T = 2s = 1024 and 2048 heavy bins per block: a batch of four transforms
+    (more selection blocks than CUs) selects on a candidate list whose LDS
+    (list, class lists, heavy pairs) leaves room for one workgroup per CU, so
+    that form runs with 16 waves; a single call (one block per CU at most)
+    holds every key in LDS instead.  The outputs are the same bit for bit."""
+    plan = gpu.Plan(N, s)
+    assert plan.info["T"] == 2 * s and plan.info["dft_path"] in (2, 4)
+    assert plan.info["K"] * plan.info["Q"] * 4 > 256
+    fs = [dev(siggen.sparse_signal(N, s, seed=60 + i, snr_db=20.0).f32) for i in range(4)]
+    say("large heavy set selection", N, s)
+    outs, counts = gpu.execute_many([plan] * 4, fs)
+    torch.cuda.synchronize()
+    for i, f in enumerate(fs):
+        w, c, n = plan.execute(f)
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        assert int(counts[i].item()) == int(n.item()), i
+        assert torch.equal(outs[i][0], w) and torch.equal(outs[i][1], c), i
+
+
 def _round_f32(q):
     """A non-negative rational rounded to the nearest float32 (ties to even),
     normal range."""
