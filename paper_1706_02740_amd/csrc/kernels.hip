@@ -2471,13 +2471,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOT
                             const int cidx = (jj << lg) + e0 / depth;
                             if (depth == 4 || (e0 & 7) == 0) ccount[cidx] = (uint8_t)n;   // (first half)
                             else ccount2[cidx] = (uint8_t)n;                                // second half
-                        } else {            // 4 / depth classes per piece
+                        } else if (depth == 2) {   // two classes per piece
 #pragma unroll
-                            for (int e = 0; e < 4; e += depth) {
-                                int n = 0;
-                                for (int k = 0; k < depth; ++k) n += ls[e + k] >= 0 ? 1 : 0;
-                                ccount[(jj << lg) + (e0 + e) / depth] = (uint8_t)n;
-                            }
+                            for (int e = 0; e < 4; e += 2)
+                                ccount[(jj << lg) + ((e0 + e) >> 1)] =
+                                    (uint8_t)((ls[e] >= 0 ? 1 : 0) + (ls[e + 1] >= 0 ? 1 : 0));
+                        } else {                   // depth 1: four classes per piece
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) ccount[(jj << lg) + e0 + e] = (uint8_t)(ls[e] >= 0 ? 1 : 0);
                         }
                     }
                 }
@@ -3057,6 +3058,7 @@ hipError_t configure_kernels(int max_lds) {
                          (const void*)k_identify<false, false, kThreads>, (const void*)k_identify<true, false, kThreads>,
                          (const void*)k_identify<false, true, kThreads>, (const void*)k_identify<true, true, kThreads>,
                          (const void*)k_identify<false, false, kIdentifyWide>,
+                         (const void*)k_identify<true, false, kIdentifyWide>,
                          (const void*)k_gather_mx<16, 2>, (const void*)k_gather_mx<64, 6>,
                          (const void*)k_gather_mx<64, 8>,
                          (const void*)k_merge, (const void*)k_dft_rows,
@@ -3177,14 +3179,18 @@ hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream
     const size_t bytes = lds & 0xffffffffu;
     const int kind = (int)((lds >> 32) & 3);
     const dim3 g(blocks), t(kThreads);
-    // a launch of few bands (a single transform or a small batch) leaves most
-    // CUs idle: give each band a workgroup of kIdentifyWide threads (its
-    // scan partials take (kIdentifyWide - kThreads) ints more).  Bitmap vote
-    // and residue identification only: the other variants need more than the
-    // 128 VGPRs such a workgroup allows.
+    // a launch of at most one band per CU (a single transform or a small
+    // batch) leaves CUs idle or with four waves each: give each band a
+    // workgroup of kIdentifyWide threads (its scan partials take
+    // (kIdentifyWide - kThreads) ints more).  Residue identification only
+    // (bitmap or key vote): the phase variants need more than the 128 VGPRs
+    // such a workgroup allows.
     const size_t wbytes = bytes + (size_t)(kIdentifyWide - kThreads) * 4;
-    if (kind == 0 && blocks <= kIdentifyWideMaxBlocks && wbytes + 256 <= (size_t)g_max_lds) {
-        hipLaunchKernelGGL((k_identify<false, false, kIdentifyWide>), g, dim3(kIdentifyWide), wbytes, st, a);
+    if (kind <= 1 && blocks <= kIdentifyWideMaxBlocks && wbytes + 256 <= (size_t)g_max_lds) {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_identify<false, false, kIdentifyWide>), g, dim3(kIdentifyWide), wbytes, st, a);
+        else
+            hipLaunchKernelGGL((k_identify<true, false, kIdentifyWide>), g, dim3(kIdentifyWide), wbytes, st, a);
         return hipGetLastError();
     }
     switch (kind) {

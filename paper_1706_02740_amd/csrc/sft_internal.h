@@ -12,7 +12,7 @@ constexpr int kMaxK = SFT_MAX_MODULI;
 constexpr int kMaxG = 7;
 constexpr int kThreads = 256;          // workgroup size of every kernel but k_dft (4 wave64)
 constexpr int kIdentifyWide = 1024;    // k_identify workgroup size for launches of at most
-constexpr int kIdentifyWideMaxBlocks = 64;   // this many bands (a few transforms)
+constexpr int kIdentifyWideMaxBlocks = 256;  // this many bands (one per CU at most)
 constexpr int kDftThreads = 512;       // k_dft workgroup size (8 wave64)
 constexpr int kBandChunk = 16;         // bands accumulated per pass of the generic gather kernel (table padding)
 constexpr int kFastTaps = 16;          // window widths with a compile-time gather kernel are at most this

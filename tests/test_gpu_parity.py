@@ -648,7 +648,10 @@ def test_largest_serving_shape_n2e26_s1024(gpu):
     512 MB of input, the split path with matrix-core columns).  Too large for
     the oracle: checked against the known spectrum instead — the support is
     exact and the coefficient error is at the noise level (per-coefficient
-    noise ~ sqrt(s) 10^(-30/20) / ghat-weighted band average; bound 1e-2)."""
+    noise ~ sqrt(s) 10^(-30/20) / ghat-weighted band average; bound 1e-2).
+    The single call (16 bands: identification with 1024-thread workgroups,
+    the vote comparing keys) and a batch of 17 copies (272 bands: 256-thread
+    workgroups) give the same outputs bit for bit."""
     N, s = 2 ** 26, 1024
     say("largest serving shape", N, s)
     plan = gpu.Plan(N, s)
@@ -663,6 +666,12 @@ def test_largest_serving_shape_n2e26_s1024(gpu):
     assert set(wg.tolist()) == set(truth)
     err = max(abs(complex(x) - truth[int(q)]) for q, x in zip(wg, cg))
     assert err < 1e-2, err
+    assert plan.info["Q"] * 17 > 256
+    outs, counts = gpu.execute_many([plan] * 17, [f] * 17)
+    torch.cuda.synchronize()
+    for i in range(17):
+        assert int(counts[i].item()) == k, i
+        assert torch.equal(outs[i][0], w) and torch.equal(outs[i][1], c), i
 
 
 def test_matrix_core_moduli_split_rule(gpu):
