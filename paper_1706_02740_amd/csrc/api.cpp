@@ -199,7 +199,7 @@ int sft_plan_create(sft_plan_t* out, int64_t N, int32_t s, const sft_params* p) 
     // when any of its plans needs it)
     pl->lds[SFT_KERNEL_IDENTIFY] = identify_lds_bytes(d, d.vote_bitmap != 0) | ((size_t)(d.vote_bitmap == 0) << 32) |
                                    ((size_t)d.phase << 33);
-    pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes();
+    pl->lds[SFT_KERNEL_MERGE] = merge_lds_bytes() | ((size_t)(d.s > kMergeWideMinS) << 32);   // bit 32: a large s
     pl->blocks[SFT_KERNEL_IDENTIFY] = identify_blocks(d);
     pl->blocks[SFT_KERNEL_MERGE] = merge_blocks(d);
     pl->info.dft_path = pl->split ? (cols_mx ? 4 : 2) : (path == 3 || (path == 0 && mx_fits)) ? 3 : 1;
@@ -494,7 +494,7 @@ using LaunchFn = hipError_t (*)(const BatchArgs&, int, size_t, hipStream_t);
 hipError_t launch_gather_l(const BatchArgs& a, int b, size_t taps, hipStream_t st) {
     return launch_gather(a, b, (int)taps, st);
 }
-hipError_t launch_merge_l(const BatchArgs& a, int b, size_t, hipStream_t st) { return launch_merge(a, b, st); }
+hipError_t launch_merge_l(const BatchArgs& a, int b, size_t lds, hipStream_t st) { return launch_merge(a, b, lds, st); }
 
 // Launch order of the pipeline and the launcher of each kernel id.
 const int kOrder[SFT_KERNEL_COUNT] = {SFT_KERNEL_GATHER,   SFT_KERNEL_GATHER_MX,   SFT_KERNEL_DFT_MX,

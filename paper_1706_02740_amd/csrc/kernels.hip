@@ -2879,7 +2879,8 @@ __device__ __forceinline__ bool merge_before(double ma, int64_t wa, double mb, i
     return ma > mb || (ma == mb && wa < wb);
 }
 
-__global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
+template <int NT>
+__global__ void __launch_bounds__(NT) k_merge(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Where at = locate(a);
     const CONSTANT SigDesc* d = desc_of(a, at.sig);
@@ -2893,14 +2894,14 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
     int32_t* off = src + kMergeCap;
     int32_t* scratch = off + SFT_MAX_BANDS + 1;
 
-    for (int bb = tid; bb < Q; bb += kThreads) off[bb] = glb(io.Rn)[bb];
+    for (int bb = tid; bb < Q; bb += NT) off[bb] = glb(io.Rn)[bb];
     __syncthreads();
-    const int total = block_exclusive_scan(off, Q, scratch);
+    const int total = block_exclusive_scan<NT>(off, Q, scratch);
     const int n = min(total, kMergeCap);
     if (tid == 0 && total > kMergeCap) atomicOr(io.status, kStatusMergeOverflow);
     // entry e of the concatenation belongs to the last band bb with off[bb] <= e
     // (a band with off[bb] <= e < off[bb + 1] is not empty); all loads at once
-    for (int e = tid; e < n; e += kThreads) {
+    for (int e = tid; e < n; e += NT) {
         int lo = 0, hi = Q - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -2913,16 +2914,17 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
         src[e] = lo * s + k;
     }
     __syncthreads();
-    if (n <= 2 * kThreads) {
+    if (n <= 512) {
         // by rank: an entry's position is the number of entries ordered before
-        // it (the frequencies of a transform are distinct, so the ranks are)
+        // it (the frequencies of a transform are distinct, so the ranks are);
+        // n compares per entry, fewer steps than the sort's up to 512 entries
         double mv[2];
         int64_t wv[2];
         int32_t sv[2];
         int rk[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int i = tid + u * kThreads;
+            const int i = tid + u * NT;
             rk[u] = -1;
             if (i < n) {
                 mv[u] = mm[i];
@@ -2946,7 +2948,7 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
     } else {   // bitonic sort of the entries padded to a power of two
         int np2 = 1;
         while (np2 < n) np2 <<= 1;
-        for (int i = n + tid; i < np2; i += kThreads) {
+        for (int i = n + tid; i < np2; i += NT) {
             mm[i] = -1.0;
             ww[i] = 0;
             src[i] = -1;
@@ -2954,7 +2956,7 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
         __syncthreads();
         for (int kk = 2; kk <= np2; kk <<= 1) {
             for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int i = tid; i < np2; i += kThreads) {
+                for (int i = tid; i < np2; i += NT) {
                     const int ixj = i ^ jj;
                     if (ixj > i) {
                         const bool up = (i & kk) == 0;
@@ -2977,7 +2979,7 @@ __global__ void __launch_bounds__(kThreads) k_merge(BatchArgs a) {
         }
     }
     const int nout = min(n, s);
-    for (int r = tid; r < s; r += kThreads) {
+    for (int r = tid; r < s; r += NT) {
         if (r < nout) {
             const double2 v = ldd2(glb(io.Rv) + src[r]);
             glb(io.out_w)[r] = ww[r];
@@ -3002,7 +3004,7 @@ size_t identify_lds_bytes(const SigDesc& d, bool bitmap) {
 }
 
 size_t merge_lds_bytes() {
-    return (size_t)kMergeCap * 20 + (SFT_MAX_BANDS + 1) * 4 + kThreads * 4 + 64;
+    return (size_t)kMergeCap * 20 + (SFT_MAX_BANDS + 1) * 4 + kMergeWide * 4 + 64;
 }
 
 int gather_blocks(const SigDesc& d) { return (d.M + kThreads - 1) / kThreads; }
@@ -3061,7 +3063,7 @@ hipError_t configure_kernels(int max_lds) {
                          (const void*)k_identify<true, false, kIdentifyWide>,
                          (const void*)k_gather_mx<16, 2>, (const void*)k_gather_mx<64, 6>,
                          (const void*)k_gather_mx<64, 8>,
-                         (const void*)k_merge, (const void*)k_dft_rows,
+                         (const void*)k_merge<kThreads>, (const void*)k_merge<kMergeWide>, (const void*)k_dft_rows,
                          (const void*)k_dft_cols, (const void*)k_dft_cols_mx, (const void*)k_select<kThreads, false>,
                          (const void*)k_select<kSelLdsThreads, false>, (const void*)k_select<kSelLdsThreads, true>};
     for (const void* k : ks) {
@@ -3202,8 +3204,14 @@ hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const BatchArgs& a, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_merge, dim3(blocks), dim3(kThreads), merge_lds_bytes(), st, a);
+hipError_t launch_merge(const BatchArgs& a, int blocks, size_t lds, hipStream_t st) {
+    // lds: bit 32 set when some transform has s > kMergeWideMinS (its band
+    // results take the sort rather than the rank form).  At most one
+    // transform per CU: 1024 threads sort each (16 waves instead of 4 per CU)
+    if ((lds >> 32) != 0 && blocks <= kMergeWideMaxBlocks)
+        hipLaunchKernelGGL((k_merge<kMergeWide>), dim3(blocks), dim3(kMergeWide), merge_lds_bytes(), st, a);
+    else
+        hipLaunchKernelGGL((k_merge<kThreads>), dim3(blocks), dim3(kThreads), merge_lds_bytes(), st, a);
     return hipGetLastError();
 }
 

@@ -18,6 +18,9 @@ constexpr int kBandChunk = 16;         // bands accumulated per pass of the gene
 constexpr int kFastTaps = 16;          // window widths with a compile-time gather kernel are at most this
 constexpr int kAcceptCap = 4096;       // bound on the accepted candidates per band kept in LDS
 constexpr int kMergeCap = 4096;        // band results merged per signal in LDS
+constexpr int kMergeWide = 1024;       // k_merge workgroup size for launches of at most
+constexpr int kMergeWideMaxBlocks = 256;   // this many transforms (one per CU at most),
+constexpr int kMergeWideMinS = 128;    // one of them with s above this
 constexpr int kSlotMap = 2048;         // k_identify: combinations whose (tuple, class) slot is tabulated in LDS
 constexpr int kRowElems = 4096;        // complex values per workgroup in the split path's row FFTs
 constexpr int kColChunk = 64;          // columns per workgroup in the split path's p-point DFTs
@@ -191,7 +194,7 @@ bool cols_mx_covers(const SigDesc& d);
 size_t cols_mx_lds_bytes(const SigDesc& d);
 hipError_t launch_dft_cols_mx(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t launch_select(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
-hipError_t launch_merge(const BatchArgs& a, int blocks, hipStream_t st);
+hipError_t launch_merge(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 hipError_t configure_kernels(int max_lds);
 // The no-alloc workspace: kScratchBytes per device, its device address on
 // device dev (the current device; looked up on the first call per device).
