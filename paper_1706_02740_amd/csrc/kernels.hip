@@ -2158,7 +2158,7 @@ __global__ void __launch_bounds__(NT) k_select(BatchArgs a) {
         const int wid = tid >> 6;
         __shared__ int32_t sh_nc, sh_dig;
         __shared__ unsigned long long sh_min;
-        constexpr int U = 8;   // loads of a thread in flight at once
+        constexpr int U = 16;  // loads of a thread in flight at once
         auto hi_of = [](float2 e) { return __float_as_uint(fmaf(e.x, e.x, e.y * e.y)); };
         if (tid == 0) {
             sh_nc = 0;
