@@ -2735,7 +2735,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOT
         if constexpr (prefetch) cur = nxt;
     }
     __syncthreads();
-    const int nacc = min(sh_cnt, acap);
+    int nacc = min(sh_cnt, acap);
     if constexpr (use_bm && !PHASE) {
         // the accepted candidates' bins in every modulus (all loads of a thread
         // issued together) and their componentwise median
@@ -2774,7 +2774,79 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((KEYVOT
         __syncthreads();
     }
     // 3. sort accepted by key descending (|z|^2 desc, w asc)
-    if (nacc <= 2 * NT) {
+    if (nacc > 512) {
+        // Many accepted entries, of which only the s largest distinct keys are
+        // kept: the copies of one frequency w (equal keys and medians) are
+        // dropped through a hash table of w over flag, the s-th largest of the
+        // remaining keys is selected, and only the kept entries (distinct
+        // keys) are sorted below.  The result is the sorted list's first s
+        // distinct entries, as without this step.
+        __shared__ int32_t sh_d, sh_k;
+        int32_t* table = flag;   // [acap], acap a power of two >= nacc: every insert finds a slot
+        for (int i = tid; i < acap; i += NT) table[i] = -1;
+        if (tid == 0) {
+            sh_d = 0;
+            sh_k = 0;
+        }
+        __syncthreads();
+        const int lgc = 31 - __clz(acap);
+        int dl = 0;   // entries this thread keeps as first copies
+        for (int i = tid; i < nacc; i += NT) {
+            const uint32_t wk = (uint32_t)akey[i];
+            uint32_t slot = (wk * 2654435761u) >> (32 - lgc);
+            for (int probe = 0; probe < acap; ++probe) {
+                const int prev = atomicCAS(&table[slot], -1, i);
+                if (prev < 0) {   // the first copy of w
+                    ++dl;
+                    break;
+                }
+                if ((uint32_t)akey[prev] == wk) {   // a later copy (entries in the table stay)
+                    akey[i] = 0;
+                    break;
+                }
+                slot = (slot + 1) & (uint32_t)(acap - 1);
+            }
+        }
+        dl = wave_inclusive_sum(dl);
+        if ((tid & 63) == 63) atomicAdd(&sh_d, dl);
+        __syncthreads();
+        const int dn = sh_d;
+        uint64_t kthr = 1;   // every remaining (nonzero) key
+        if (dn > d->s) {
+            // the histogram over the slot map, free after the combinations
+            static_assert(kSlotMap * 2 >= kSelBins * 4, "selection histogram in the slot map");
+            auto each = [&](auto f) {
+                for (int i = tid; i < nacc; i += NT) {
+                    const uint64_t k = akey[i];
+                    if (k != 0) f((uint32_t)(k >> 32), [k] { return k; });
+                }
+            };
+            kthr = kth_largest<NT>(each, dn, d->s, reinterpret_cast<int32_t*>(cmap), scratch);
+        }
+        // the kept entries (at most s) to the slot prefix sums' space, free
+        // now ((2 s1 + 2) * 4 >= 16 s bytes as s1 >= 2 s; 8-byte aligned)
+        uint64_t* kk = reinterpret_cast<uint64_t*>(pre);
+        float2* kz = reinterpret_cast<float2*>(kk + d->s);
+        for (int i = tid; i < nacc; i += NT) {
+            const uint64_t k = akey[i];
+            if (k != 0 && k >= kthr) {
+                const int pos = atomicAdd(&sh_k, 1);
+                if (pos < d->s) {   // exactly min(dn, s) entries pass; the bound only guards the space
+                    kk[pos] = k;
+                    kz[pos] = az[i];
+                }
+            }
+        }
+        __syncthreads();
+        const int kn = min(sh_k, d->s);
+        for (int i = tid; i < kn; i += NT) {
+            akey[i] = kk[i];
+            az[i] = kz[i];
+        }
+        __syncthreads();
+        nacc = kn;
+    }
+    if (nacc <= 512) {
         // by rank: an entry's position is the number of entries ahead of it
         // (a larger key, or an equal key at a lower index)
         uint64_t kk[2];
