@@ -3254,13 +3254,15 @@ hipError_t launch_identify(const BatchArgs& a, int blocks, size_t lds, hipStream
     const int kind = (int)((lds >> 32) & 3);
     const dim3 g(blocks), t(kThreads);
     // a launch of at most one band per CU (a single transform or a small
-    // batch) leaves CUs idle or with four waves each: give each band a
-    // workgroup of kIdentifyWide threads (its scan partials take
+    // batch), or of bands whose LDS leaves room for one workgroup per CU
+    // (large s), runs four waves per CU at 256 threads: give each band a
+    // workgroup of kIdentifyWide threads instead (its scan partials take
     // (kIdentifyWide - kThreads) ints more).  Residue identification only
     // (bitmap or key vote): the phase variants need more than the 128 VGPRs
     // such a workgroup allows.
     const size_t wbytes = bytes + (size_t)(kIdentifyWide - kThreads) * 4;
-    if (kind <= 1 && blocks <= kIdentifyWideMaxBlocks && wbytes + 256 <= (size_t)g_max_lds) {
+    if (kind <= 1 && (blocks <= kIdentifyWideMaxBlocks || 2 * bytes > (size_t)g_max_lds) &&
+        wbytes + 256 <= (size_t)g_max_lds) {
         if (kind == 0)
             hipLaunchKernelGGL((k_identify<false, false, kIdentifyWide>), g, dim3(kIdentifyWide), wbytes, st, a);
         else

@@ -468,19 +468,22 @@ def test_split_selection_variants_agree(gpu, kind, path):
         assert np.array_equal(outs[i][1].cpu().numpy(), c.cpu().numpy()), i
 
 
-@pytest.mark.parametrize("N,s", [(2 ** 22, 512), (2 ** 24, 1024)])
-def test_large_heavy_set_selection_batch_equals_single(gpu, N, s):
-    """T = 2s = 1024 and 2048 heavy bins per block: a batch of four transforms
-    (more selection blocks than CUs) selects on a candidate list whose LDS
-    (list, class lists, heavy pairs) leaves room for one workgroup per CU, so
-    that form runs with 16 waves; a single call (one block per CU at most)
-    holds every key in LDS instead.  The outputs are the same bit for bit."""
+@pytest.mark.parametrize("N,s,B", [(2 ** 22, 512, 17), (2 ** 24, 1024, 4)])
+def test_large_heavy_set_selection_batch_equals_single(gpu, N, s, B):
+    """T = 2s = 1024 and 2048 heavy bins per block: a batch (more selection
+    blocks than CUs) selects on a candidate list whose LDS (list, class
+    lists, heavy pairs) leaves room for one workgroup per CU, so that form
+    runs with 16 waves; a single call (one block per CU at most) holds every
+    key in LDS instead.  The 17 transforms of the first batch give 272 bands,
+    more than CUs, whose identification LDS also leaves room for one
+    workgroup per CU: 1024 threads there too.  The outputs are the same bit
+    for bit."""
     plan = gpu.Plan(N, s)
     assert plan.info["T"] == 2 * s and plan.info["dft_path"] in (2, 4)
-    assert plan.info["K"] * plan.info["Q"] * 4 > 256
-    fs = [dev(siggen.sparse_signal(N, s, seed=60 + i, snr_db=20.0).f32) for i in range(4)]
-    say("large heavy set selection", N, s)
-    outs, counts = gpu.execute_many([plan] * 4, fs)
+    assert plan.info["K"] * plan.info["Q"] * B > 256
+    fs = [dev(siggen.sparse_signal(N, s, seed=60 + i, snr_db=20.0).f32) for i in range(B)]
+    say("large heavy set selection", N, s, B)
+    outs, counts = gpu.execute_many([plan] * B, fs)
     torch.cuda.synchronize()
     for i, f in enumerate(fs):
         w, c, n = plan.execute(f)
