@@ -31,6 +31,16 @@ def test_library_exports_every_declared_symbol():
     assert set(sftlib.EXPORTED) == set(names)
 
 
+def test_binding_fetch_kinds_match_the_header():
+    """Every SFT_FETCH_* kind the header defines has the same value in the
+    binding (the class lists' kind included)."""
+    text = open(os.path.join(ROOT, "include", "sft.h")).read()
+    kinds = dict(re.findall(r"#define SFT_FETCH_([A-Z_]+)\s+(\d+)", text))
+    assert "CLASSES" in kinds and len(kinds) >= 7
+    for name, value in kinds.items():
+        assert getattr(sftlib, "FETCH_" + name) == int(value), name
+
+
 def test_symbols_have_c_linkage():
     out = subprocess.run(["nm", "-D", "--defined-only", sftlib.LIB_PATH], capture_output=True, text=True).stdout
     assert not re.search(r"\bT _Z\w*sft_(execute|plan)", out)
